@@ -1,0 +1,520 @@
+// WENO-ZN reference oracle -- TEST INFRASTRUCTURE ONLY.
+//
+// Plain, serial-by-construction, slow CPU implementation of the finite-difference
+// WENO-ZN scheme of Shen, Zhang, Li and Peng, "A novel method for constructing high
+// accurate and robust WENO-Z type scheme" (arXiv 2004.07954).  It exists so that the
+// HIP library can be checked against something written directly from the paper.
+// Only tests, the smoke check and the CPU-baseline leg of the benchmark may load it;
+// the product path never does.  It shares no code with the HIP library.
+//
+// Everything is templated on the scalar type T:
+//   double              -- the reference precision of all parity checks;
+//   __float128          -- for the paper's critical-point table, whose errors fall
+//                          below fp64 resolution;
+//   std::complex<double>-- complex-step directional derivatives for the reference
+//                          gradient of the discrete adjoint.
+// Formulas are evaluated in the literal order the paper prints them, and the file is
+// compiled with -ffp-contract=off so that no fused multiply-add changes that order.
+// OpenMP pragmas only split independent per-cell loops; the max reduction is exact,
+// so results do not depend on the thread count.
+//
+// Readings taken where the paper is silent (each is listed with its evidence in the
+// design notes):
+//   * eps of WENO-ZN is a parameter; 1e-40 reproduces the critical-point table.
+//   * the exponent on tau8/(IS_k+eps) is a parameter q (paper: 1); the exponent on
+//     the ratio inside C is p_C (paper: 2).
+//   * tau inside C is tau5 = |IS0 - IS2|.
+//   * f^- is reconstructed with the five points mirrored about x_{i+1/2}.
+//   * Lax-Friedrichs alpha is the max of |u|+c over interior cells, recomputed for
+//     every right-hand-side evaluation unless a frozen value is supplied.
+//   * transmissive boundaries copy the edge cell into the three ghost cells.
+//   * TVD-RK3 is the Shu-Osher three-stage scheme; dt comes from U^n.
+
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+#include <algorithm>
+#include <quadmath.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef __float128 f128;
+typedef std::complex<double> cplx;
+
+// ---------------------------------------------------------------- scalar helpers
+static inline double absv(double x) { return std::fabs(x); }
+static inline f128 absv(f128 x) { return fabsq(x); }
+// |z| for the complex step: the analytic continuation of |x| away from x = 0.
+static inline cplx absv(cplx z) { return z.real() < 0.0 ? -z : z; }
+
+static inline double realv(double x) { return x; }
+static inline double realv(f128 x) { return (double)x; }
+static inline double realv(cplx z) { return z.real(); }
+
+template <class T> static inline T sq(T x) { return x * x; }
+template <class T> static inline T ipow(T x, int p) {
+  T r = x;
+  for (int i = 1; i < p; ++i) r = r * x;
+  return r;
+}
+
+// Scheme selector.  Only WZN_ZN is the paper's method; Z and JS are the comparison
+// weights the paper restates (Sec. 2.1 eq:5, Sec. 2.2 eq:15), kept here only to check
+// the test harness against the WENO-Z column of the critical-point table and as a
+// negative control for the convergence-order tests.
+enum { ORC_ZN = 0, ORC_Z = 1, ORC_JS = 2 };
+
+struct OrcParams {       // mirrored by a ctypes Structure in oracle/binding.py
+  int32_t scheme;        // ORC_ZN / ORC_Z / ORC_JS
+  int32_t p_C;           // exponent in C (eq:function): 2
+  int32_t q;             // exponent on tau/(IS_k+eps): ZN 1 (eq:new), Z q of eq:15
+  int32_t pad;
+  double A;              // constant of eq:function: 10
+  double eps;            // epsilon
+};
+
+template <class T> struct Recon {
+  T IS[3], tau5, tau8, C, alpha[3], omega[3], q[3], fhat;
+};
+
+// One fifth-order reconstruction of f_{i+1/2} from (f_{i-2}, ..., f_{i+2}) = (a..e).
+//   candidate fluxes            Sec. 2.1, eq:4
+//   Jiang-Shu indicators IS_k   Sec. 2.1, eq:isjiang
+//   tau5 = |IS0 - IS2|          Sec. 2.2, eq:tao5 and Sec. 3, eq:tau
+//   tau8                        Sec. 3, eq:tau8
+//   C                           Sec. 3, eq:function
+//   alpha_k (WENO-ZN)           Sec. 3, eq:new
+//   omega_k, f_hat              Sec. 2.1, eq:5 and eq:3, with c = (0.1, 0.6, 0.3)
+template <class T>
+static Recon<T> reconstruct(T a, T b, T c, T d, T e, const OrcParams& P) {
+  Recon<T> r;
+  const T eps = T(P.eps);
+  const T A = T(P.A);
+  const T ck[3] = {T(1) / T(10), T(6) / T(10), T(3) / T(10)};
+
+  r.q[0] = T(1) / T(3) * a - T(7) / T(6) * b + T(11) / T(6) * c;
+  r.q[1] = -T(1) / T(6) * b + T(5) / T(6) * c + T(1) / T(3) * d;
+  r.q[2] = T(1) / T(3) * c + T(5) / T(6) * d - T(1) / T(6) * e;
+
+  r.IS[0] = T(13) / T(12) * sq(a - T(2) * b + c) + T(1) / T(4) * sq(a - T(4) * b + T(3) * c);
+  r.IS[1] = T(13) / T(12) * sq(b - T(2) * c + d) + T(1) / T(4) * sq(b - d);
+  r.IS[2] = T(13) / T(12) * sq(c - T(2) * d + e) + T(1) / T(4) * sq(T(3) * c - T(4) * d + e);
+
+  r.tau5 = absv(r.IS[0] - r.IS[2]);
+  r.tau8 = sq(a - T(4) * b + T(6) * c - T(4) * d + e);
+  r.C = A * ipow((r.IS[0] + r.IS[2] - r.tau5 + eps) / (r.tau5 + eps), P.p_C);
+
+  for (int k = 0; k < 3; ++k) {
+    if (P.scheme == ORC_ZN)
+      r.alpha[k] = ck[k] * (r.C + ipow(r.tau8 / (r.IS[k] + eps), P.q));
+    else if (P.scheme == ORC_Z)
+      r.alpha[k] = ck[k] * (T(1) + ipow(r.tau5 / (r.IS[k] + eps), P.q));
+    else
+      r.alpha[k] = ck[k] / sq(r.IS[k] + eps);
+  }
+  const T sum = r.alpha[0] + r.alpha[1] + r.alpha[2];
+  for (int k = 0; k < 3; ++k) r.omega[k] = r.alpha[k] / sum;
+  r.fhat = r.omega[0] * r.q[0] + r.omega[1] * r.q[1] + r.omega[2] * r.q[2];
+  return r;
+}
+
+// ---------------------------------------------------------------- physics
+// Systems: 0 = linear advection u_t + a u_x = 0 (Sec. 4.2, eq:26);
+//          1 = 1D Euler, U = (rho, rho u, E) (Sec. 4.3);
+//          2 = 2D Euler, U = (rho, rho u, rho v, E) (Sec. 4.4, eq:2d).
+enum { SYS_ADV = 0, SYS_EULER1 = 1, SYS_EULER2 = 2 };
+enum { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1 };
+
+struct Phys {
+  double a;      // advection speed
+  double gamma;  // ratio of specific heats
+};
+
+// 1D Euler: u = m/rho; p from E = p/(gamma-1) + rho u^2 / 2; F = (rho u, rho u^2 + p, u (E + p)).
+template <class T>
+static void euler1_flux(const T* U, T* F, const Phys& ph) {
+  const T rho = U[0], m = U[1], E = U[2];
+  const T u = m / rho;
+  const T p = (T(ph.gamma) - T(1)) * (E - T(1) / T(2) * rho * u * u);
+  F[0] = rho * u;
+  F[1] = rho * u * u + p;
+  F[2] = u * (E + p);
+}
+
+static double euler1_speed(const double* U, const Phys& ph) {
+  const double rho = U[0], m = U[1], E = U[2];
+  const double u = m / rho;
+  const double p = (ph.gamma - 1.0) * (E - 0.5 * rho * u * u);
+  return std::fabs(u) + std::sqrt(ph.gamma * p / rho);
+}
+
+// 2D Euler, E = p/(gamma-1) + rho (u^2 + v^2)/2;
+// F = (rho u, rho u^2 + p, rho u v, u (E + p)), G = (rho v, rho u v, rho v^2 + p, v (E + p)).
+template <class T>
+static void euler2_flux(const T* U, T* F, T* G, const Phys& ph) {
+  const T rho = U[0], mx = U[1], my = U[2], E = U[3];
+  const T u = mx / rho, v = my / rho;
+  const T p = (T(ph.gamma) - T(1)) * (E - rho / T(2) * (u * u + v * v));
+  F[0] = rho * u; F[1] = rho * u * u + p; F[2] = rho * u * v; F[3] = u * (E + p);
+  G[0] = rho * v; G[1] = rho * u * v; G[2] = rho * v * v + p; G[3] = v * (E + p);
+}
+
+static void euler2_speeds(const double* U, const Phys& ph, double* sx, double* sy) {
+  const double rho = U[0], mx = U[1], my = U[2], E = U[3];
+  const double u = mx / rho, v = my / rho;
+  const double p = (ph.gamma - 1.0) * (E - rho / 2.0 * (u * u + v * v));
+  const double c = std::sqrt(ph.gamma * p / rho);
+  *sx = std::fabs(u) + c;
+  *sy = std::fabs(v) + c;
+}
+
+static int nvar_of(int sys) { return sys == SYS_ADV ? 1 : (sys == SYS_EULER1 ? 3 : 4); }
+
+// Ghost index map for three ghost cells per side (Sec. 4.2, eq:26 periodic; the
+// transmissive rule copies the edge cell).
+static inline int64_t ghost_index(int64_t g, int64_t n, int bc) {
+  if (g >= 0 && g < n) return g;
+  if (bc == BC_PERIODIC) return ((g % n) + n) % n;
+  return g < 0 ? 0 : n - 1;
+}
+
+// ---------------------------------------------------------------- 1D right-hand side
+// Global Lax-Friedrichs alpha for the 1D systems: max over interior cells of the
+// largest wave speed (Sec. 4.3: |u| + c with c = sqrt(gamma p / rho); advection: |a|).
+static double lf_alpha_1d(int sys, int64_t n, const double* u, const Phys& ph) {
+  if (sys == SYS_ADV) return std::fabs(ph.a);
+  double m = 0.0;
+#pragma omp parallel for reduction(max : m)
+  for (int64_t i = 0; i < n; ++i) {
+    double U[3] = {u[i], u[n + i], u[2 * n + i]};
+    m = std::max(m, euler1_speed(U, ph));
+  }
+  return m;
+}
+
+// L_i = -(fhat_{i+1/2} - fhat_{i-1/2}) / dx (Sec. 2, eq:2), with
+// fhat = fhat^+ + fhat^-, fhat^+ from (f+_{i-2..i+2}) and fhat^- from the mirrored
+// (f-_{i+3}, ..., f-_{i-1}) (the symmetric rule about x_{i+1/2}, Sec. 2), and the
+// Lax-Friedrichs split f^{+-} = (F(U) +- alpha U)/2 applied component by component.
+template <class T>
+static void rhs_1d(int sys, int bc, int64_t n, const T* u, T* dudt, T dx, double alpha,
+                   const OrcParams& P, const Phys& ph) {
+  const int nv = nvar_of(sys);
+  const int64_t np = n + 6;  // padded: cell i lives at i + 3
+  std::vector<T> Up(nv * np), fp(nv * np), fm(nv * np), fh(nv * (n + 1));
+  for (int v = 0; v < nv; ++v)
+    for (int64_t g = -3; g < n + 3; ++g) Up[v * np + g + 3] = u[v * n + ghost_index(g, n, bc)];
+
+#pragma omp parallel for
+  for (int64_t j = 0; j < np; ++j) {
+    T U[3], F[3];
+    for (int v = 0; v < nv; ++v) U[v] = Up[v * np + j];
+    if (sys == SYS_ADV) F[0] = T(ph.a) * U[0];
+    else euler1_flux(U, F, ph);
+    for (int v = 0; v < nv; ++v) {
+      fp[v * np + j] = T(1) / T(2) * (F[v] + T(alpha) * U[v]);
+      fm[v * np + j] = T(1) / T(2) * (F[v] - T(alpha) * U[v]);
+    }
+  }
+  // interface k <-> x_{i+1/2} with i = k - 1, k = 0..n
+#pragma omp parallel for
+  for (int64_t k = 0; k <= n; ++k) {
+    const int64_t i = k - 1 + 3;  // padded index of cell i
+    for (int v = 0; v < nv; ++v) {
+      const T* P_ = &fp[v * np];
+      const T* M_ = &fm[v * np];
+      T hp = reconstruct(P_[i - 2], P_[i - 1], P_[i], P_[i + 1], P_[i + 2], P).fhat;
+      T hm = reconstruct(M_[i + 3], M_[i + 2], M_[i + 1], M_[i], M_[i - 1], P).fhat;
+      fh[v * (n + 1) + k] = hp + hm;
+    }
+  }
+  for (int v = 0; v < nv; ++v)
+    for (int64_t i = 0; i < n; ++i)
+      dudt[v * n + i] = -(fh[v * (n + 1) + i + 1] - fh[v * (n + 1) + i]) / dx;
+}
+
+// ---------------------------------------------------------------- 2D right-hand side
+// Dimension by dimension (Sec. 4.4, eq:2d): L = -(Fhat_{i+1/2,j} - Fhat_{i-1/2,j})/dx
+// - (Ghat_{i,j+1/2} - Ghat_{i,j-1/2})/dy, each a 1D WENO-ZN reconstruction of the
+// Lax-Friedrichs-split flux along its own direction with its own global alpha.
+// Layout [4][ny][nx], x fastest.
+template <class T>
+static void rhs_2d(int bcx, int bcy, int64_t nx, int64_t ny, const T* u, T* dudt, T dx, T dy,
+                   double ax, double ay, const OrcParams& P, const Phys& ph) {
+  const int64_t N = nx * ny;
+#pragma omp parallel for
+  for (int64_t j = 0; j < ny; ++j) {
+    // x sweep along row j
+    const int64_t np = nx + 6;
+    std::vector<T> fp(4 * np), fm(4 * np), fh(4 * (nx + 1));
+    for (int64_t g = -3; g < nx + 3; ++g) {
+      const int64_t gi = ghost_index(g, nx, bcx);
+      T U[4], F[4], G[4];
+      for (int v = 0; v < 4; ++v) U[v] = u[v * N + j * nx + gi];
+      euler2_flux(U, F, G, ph);
+      for (int v = 0; v < 4; ++v) {
+        fp[v * np + g + 3] = T(1) / T(2) * (F[v] + T(ax) * U[v]);
+        fm[v * np + g + 3] = T(1) / T(2) * (F[v] - T(ax) * U[v]);
+      }
+    }
+    for (int64_t k = 0; k <= nx; ++k) {
+      const int64_t i = k - 1 + 3;
+      for (int v = 0; v < 4; ++v) {
+        const T* P_ = &fp[v * np];
+        const T* M_ = &fm[v * np];
+        fh[v * (nx + 1) + k] =
+            reconstruct(P_[i - 2], P_[i - 1], P_[i], P_[i + 1], P_[i + 2], P).fhat +
+            reconstruct(M_[i + 3], M_[i + 2], M_[i + 1], M_[i], M_[i - 1], P).fhat;
+      }
+    }
+    for (int v = 0; v < 4; ++v)
+      for (int64_t i = 0; i < nx; ++i)
+        dudt[v * N + j * nx + i] = -(fh[v * (nx + 1) + i + 1] - fh[v * (nx + 1) + i]) / dx;
+  }
+#pragma omp parallel for
+  for (int64_t i = 0; i < nx; ++i) {
+    // y sweep along column i
+    const int64_t np = ny + 6;
+    std::vector<T> gp(4 * np), gm(4 * np), gh(4 * (ny + 1));
+    for (int64_t g = -3; g < ny + 3; ++g) {
+      const int64_t gj = ghost_index(g, ny, bcy);
+      T U[4], F[4], G[4];
+      for (int v = 0; v < 4; ++v) U[v] = u[v * N + gj * nx + i];
+      euler2_flux(U, F, G, ph);
+      for (int v = 0; v < 4; ++v) {
+        gp[v * np + g + 3] = T(1) / T(2) * (G[v] + T(ay) * U[v]);
+        gm[v * np + g + 3] = T(1) / T(2) * (G[v] - T(ay) * U[v]);
+      }
+    }
+    for (int64_t k = 0; k <= ny; ++k) {
+      const int64_t jj = k - 1 + 3;
+      for (int v = 0; v < 4; ++v) {
+        const T* P_ = &gp[v * np];
+        const T* M_ = &gm[v * np];
+        gh[v * (ny + 1) + k] =
+            reconstruct(P_[jj - 2], P_[jj - 1], P_[jj], P_[jj + 1], P_[jj + 2], P).fhat +
+            reconstruct(M_[jj + 3], M_[jj + 2], M_[jj + 1], M_[jj], M_[jj - 1], P).fhat;
+      }
+    }
+    for (int v = 0; v < 4; ++v)
+      for (int64_t j = 0; j < ny; ++j)
+        dudt[v * N + j * nx + i] += -(gh[v * (ny + 1) + j + 1] - gh[v * (ny + 1) + j]) / dy;
+  }
+}
+
+static void lf_alpha_2d(int64_t N, const double* u, const Phys& ph, double* ax, double* ay) {
+  double mx = 0.0, my = 0.0;
+#pragma omp parallel for reduction(max : mx, my)
+  for (int64_t k = 0; k < N; ++k) {
+    double U[4] = {u[k], u[N + k], u[2 * N + k], u[3 * N + k]};
+    double sx, sy;
+    euler2_speeds(U, ph, &sx, &sy);
+    mx = std::max(mx, sx);
+    my = std::max(my, sy);
+  }
+  *ax = mx;
+  *ay = my;
+}
+
+// ---------------------------------------------------------------- TVD-RK3
+// Shu-Osher third-order TVD Runge-Kutta (cited in Sec. 4; standard form):
+//   U1 = U^n + dt L(U^n)
+//   U2 = 3/4 U^n + 1/4 (U1 + dt L(U1))
+//   U^{n+1} = 1/3 U^n + 2/3 (U2 + dt L(U2))
+static const double RK_A[3] = {0.0, 3.0 / 4.0, 1.0 / 3.0};
+static const double RK_B[3] = {1.0, 1.0 / 4.0, 2.0 / 3.0};
+
+extern "C" {
+
+typedef struct {
+  double alpha_used[3];  // LF alpha of each stage (x direction)
+  double alpha_used_y[3];
+  double dt;
+} OrcStepInfo;
+
+// ---- single reconstruction, all intermediate quantities (fp64)
+// out: IS0 IS1 IS2 tau5 tau8 C alpha0..2 omega0..2 q0..2 fhat  (16 doubles)
+void orc_reconstruct_f64(const double* f5, const OrcParams* P, double* out) {
+  Recon<double> r = reconstruct(f5[0], f5[1], f5[2], f5[3], f5[4], *P);
+  double* o = out;
+  for (int k = 0; k < 3; ++k) *o++ = r.IS[k];
+  *o++ = r.tau5; *o++ = r.tau8; *o++ = r.C;
+  for (int k = 0; k < 3; ++k) *o++ = r.alpha[k];
+  for (int k = 0; k < 3; ++k) *o++ = r.omega[k];
+  for (int k = 0; k < 3; ++k) *o++ = r.q[k];
+  *o++ = r.fhat;
+}
+
+// Same in __float128; inputs/outputs as (hi, lo) pairs of doubles, value = hi + lo.
+void orc_reconstruct_f128(const double* f5hi, const double* f5lo, const OrcParams* P,
+                          double* out_hi, double* out_lo) {
+  f128 f[5];
+  for (int k = 0; k < 5; ++k) f[k] = (f128)f5hi[k] + (f128)f5lo[k];
+  Recon<f128> r = reconstruct(f[0], f[1], f[2], f[3], f[4], *P);
+  f128 vals[16];
+  f128* o = vals;
+  for (int k = 0; k < 3; ++k) *o++ = r.IS[k];
+  *o++ = r.tau5; *o++ = r.tau8; *o++ = r.C;
+  for (int k = 0; k < 3; ++k) *o++ = r.alpha[k];
+  for (int k = 0; k < 3; ++k) *o++ = r.omega[k];
+  for (int k = 0; k < 3; ++k) *o++ = r.q[k];
+  *o++ = r.fhat;
+  for (int k = 0; k < 16; ++k) {
+    out_hi[k] = (double)vals[k];
+    out_lo[k] = (double)(vals[k] - (f128)out_hi[k]);
+  }
+}
+
+// ---- 1D RHS (fp64).  alpha_in < 0: compute the global LF alpha from u.
+double orc_rhs_1d_f64(int sys, int bc, int64_t n, const double* u, double* dudt, double dx,
+                      double alpha_in, const OrcParams* P, double a, double gamma) {
+  Phys ph{a, gamma};
+  double alpha = alpha_in >= 0.0 ? alpha_in : lf_alpha_1d(sys, n, u, ph);
+  rhs_1d<double>(sys, bc, n, u, dudt, dx, alpha, *P, ph);
+  return alpha;
+}
+
+// ---- 1D RHS in __float128 (hi/lo pairs); alpha must be supplied.
+void orc_rhs_1d_f128(int sys, int bc, int64_t n, const double* uhi, const double* ulo,
+                     double* dhi, double* dlo, double dx_hi, double dx_lo, double alpha,
+                     const OrcParams* P, double a, double gamma) {
+  Phys ph{a, gamma};
+  const int nv = nvar_of(sys);
+  std::vector<f128> u(nv * n), d(nv * n);
+  for (int64_t k = 0; k < nv * n; ++k) u[k] = (f128)uhi[k] + (f128)ulo[k];
+  rhs_1d<f128>(sys, bc, n, u.data(), d.data(), (f128)dx_hi + (f128)dx_lo, alpha, *P, ph);
+  for (int64_t k = 0; k < nv * n; ++k) {
+    dhi[k] = (double)d[k];
+    dlo[k] = (double)(d[k] - (f128)dhi[k]);
+  }
+}
+
+// ---- 1D RHS with complex inputs (complex-step derivatives); alpha must be supplied.
+// Arrays are interleaved (re, im) pairs.
+void orc_rhs_1d_c128(int sys, int bc, int64_t n, const double* u_ri, double* d_ri, double dx,
+                     double alpha, const OrcParams* P, double a, double gamma) {
+  Phys ph{a, gamma};
+  const int nv = nvar_of(sys);
+  std::vector<cplx> u(nv * n), d(nv * n);
+  for (int64_t k = 0; k < nv * n; ++k) u[k] = cplx(u_ri[2 * k], u_ri[2 * k + 1]);
+  rhs_1d<cplx>(sys, bc, n, u.data(), d.data(), cplx(dx, 0.0), alpha, *P, ph);
+  for (int64_t k = 0; k < nv * n; ++k) {
+    d_ri[2 * k] = d[k].real();
+    d_ri[2 * k + 1] = d[k].imag();
+  }
+}
+
+// ---- one TVD-RK3 step, 1D (fp64), in place on u.
+// dt_in <= 0: dt = cfl dx / max(|u|+c) of U^n (Sec. 4.3); advection uses |a|.
+// alpha_in: NULL -> LF alpha recomputed for every stage from that stage's input;
+//           otherwise alpha_in[s] is the frozen alpha of stage s.
+void orc_rk3_step_1d_f64(int sys, int bc, int64_t n, double* u, double dx, double cfl,
+                         double dt_in, const double* alpha_in, const OrcParams* P, double a,
+                         double gamma, OrcStepInfo* info) {
+  Phys ph{a, gamma};
+  const int nv = nvar_of(sys);
+  const int64_t M = nv * n;
+  std::vector<double> un(u, u + M), us(u, u + M), L(M);
+  const double speed = lf_alpha_1d(sys, n, u, ph);
+  const double dt = dt_in > 0.0 ? dt_in : cfl * dx / speed;
+  for (int s = 0; s < 3; ++s) {
+    const double alpha = alpha_in ? alpha_in[s] : lf_alpha_1d(sys, n, us.data(), ph);
+    rhs_1d<double>(sys, bc, n, us.data(), L.data(), dx, alpha, *P, ph);
+    for (int64_t k = 0; k < M; ++k)
+      us[k] = RK_A[s] * un[k] + RK_B[s] * (us[k] + dt * L[k]);
+    if (info) info->alpha_used[s] = alpha;
+  }
+  std::memcpy(u, us.data(), sizeof(double) * M);
+  if (info) info->dt = dt;
+}
+
+// ---- nsteps TVD-RK3 steps, 1D.  dt_in: NULL (CFL) or [nsteps];
+// alpha_in: NULL (reduce) or [3*nsteps]; dt_out/alpha_out may be NULL.
+void orc_rk3_run_1d_f64(int sys, int bc, int64_t n, double* u, double dx, double cfl,
+                        int32_t nsteps, const double* dt_in, const double* alpha_in,
+                        const OrcParams* P, double a, double gamma, double* dt_out,
+                        double* alpha_out) {
+  for (int32_t s = 0; s < nsteps; ++s) {
+    OrcStepInfo info;
+    orc_rk3_step_1d_f64(sys, bc, n, u, dx, cfl, dt_in ? dt_in[s] : -1.0,
+                        alpha_in ? alpha_in + 3 * s : nullptr, P, a, gamma, &info);
+    if (dt_out) dt_out[s] = info.dt;
+    if (alpha_out)
+      for (int k = 0; k < 3; ++k) alpha_out[3 * s + k] = info.alpha_used[k];
+  }
+}
+
+// ---- one TVD-RK3 step with complex state (complex-step derivatives of the step map),
+// dt and the three stage alphas frozen.  u_ri: interleaved (re, im), updated in place.
+void orc_rk3_step_1d_c128(int sys, int bc, int64_t n, double* u_ri, double dx, double dt,
+                          const double* alpha3, const OrcParams* P, double a, double gamma) {
+  Phys ph{a, gamma};
+  const int nv = nvar_of(sys);
+  const int64_t M = nv * n;
+  std::vector<cplx> un(M), us(M), L(M);
+  for (int64_t k = 0; k < M; ++k) un[k] = us[k] = cplx(u_ri[2 * k], u_ri[2 * k + 1]);
+  for (int s = 0; s < 3; ++s) {
+    rhs_1d<cplx>(sys, bc, n, us.data(), L.data(), cplx(dx, 0.0), alpha3[s], *P, ph);
+    for (int64_t k = 0; k < M; ++k)
+      us[k] = cplx(RK_A[s]) * un[k] + cplx(RK_B[s]) * (us[k] + cplx(dt) * L[k]);
+  }
+  for (int64_t k = 0; k < M; ++k) {
+    u_ri[2 * k] = us[k].real();
+    u_ri[2 * k + 1] = us[k].imag();
+  }
+}
+
+// ---- 2D RHS (fp64).  alpha_x/alpha_y < 0: compute from u.  Returns both alphas.
+void orc_rhs_2d_f64(int bcx, int bcy, int64_t nx, int64_t ny, const double* u, double* dudt,
+                    double dx, double dy, double alpha_x, double alpha_y, const OrcParams* P,
+                    double gamma, double* alpha_used) {
+  Phys ph{0.0, gamma};
+  double ax, ay;
+  lf_alpha_2d(nx * ny, u, ph, &ax, &ay);
+  if (alpha_x >= 0.0) ax = alpha_x;
+  if (alpha_y >= 0.0) ay = alpha_y;
+  rhs_2d<double>(bcx, bcy, nx, ny, u, dudt, dx, dy, ax, ay, *P, ph);
+  if (alpha_used) { alpha_used[0] = ax; alpha_used[1] = ay; }
+}
+
+// ---- nsteps TVD-RK3 steps, 2D, in place.  dt from U^n as
+// dt = cfl dtx dty / (dtx + dty), dtx = dx / max(|u|+c), dty = dy / max(|v|+c)
+// (Sec. 4.4).  LF alphas recomputed for every stage.
+void orc_rk3_run_2d_f64(int bcx, int bcy, int64_t nx, int64_t ny, double* u, double dx,
+                        double dy, double cfl, int32_t nsteps, const double* dt_in,
+                        const OrcParams* P, double gamma, double* dt_out) {
+  Phys ph{0.0, gamma};
+  const int64_t M = 4 * nx * ny;
+  std::vector<double> un(M), us(M), L(M);
+  for (int32_t st = 0; st < nsteps; ++st) {
+    std::memcpy(un.data(), u, sizeof(double) * M);
+    std::memcpy(us.data(), u, sizeof(double) * M);
+    double sx, sy;
+    lf_alpha_2d(nx * ny, u, ph, &sx, &sy);
+    const double dtx = dx / sx, dty = dy / sy;
+    const double dt = dt_in ? dt_in[st] : cfl * dtx * dty / (dtx + dty);
+    for (int s = 0; s < 3; ++s) {
+      double ax, ay;
+      lf_alpha_2d(nx * ny, us.data(), ph, &ax, &ay);
+      rhs_2d<double>(bcx, bcy, nx, ny, us.data(), L.data(), dx, dy, ax, ay, *P, ph);
+      for (int64_t k = 0; k < M; ++k)
+        us[k] = RK_A[s] * un[k] + RK_B[s] * (us[k] + dt * L[k]);
+    }
+    std::memcpy(u, us.data(), sizeof(double) * M);
+    if (dt_out) dt_out[st] = dt;
+  }
+}
+
+// Thread count the OpenMP runtime would use (reported with CPU timings).
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+}  // extern "C"

@@ -1,0 +1,240 @@
+"""Pins of the oracle's full right-hand side and TVD-RK3 driver: closed-form solutions,
+convergence orders, conservation, self-similarity and symmetries."""
+import numpy as np
+import pytest
+
+from paper_2004_07954_amd import inputs as I
+
+
+def _orders(errs):
+    return [np.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+
+
+def _advect(orc, n, T=2.0, prm=None, dt_pow=5.0 / 3.0):
+    u0, dx = I.advection_smooth(n)
+    dt0 = 0.5 * dx**dt_pow
+    nsteps = int(np.ceil(T / dt0 - 1e-12))
+    dt = T / nsteps
+    u, _, _ = orc.rk3_run_1d(u0, dx, nsteps, dt=dt, sys=orc.SYS_ADV, bc=orc.BC_PERIODIC,
+                             prm=prm)
+    x, _ = I.cell_centres(-1.0, 1.0, n)
+    e = u[0] - I.advection_smooth_exact(x, T)
+    return np.mean(np.abs(e)), np.max(np.abs(e))
+
+
+@pytest.mark.slow
+def test_advection_fifth_order(orc):
+    """Smooth periodic advection u_t + u_x = 0 (Sec. 4.2, eq:26) against the exact
+    solution u0(x - t), with dt ~ dx^(5/3) so that RK3's error is O(dx^5): L1 and Linf
+    orders reach 5 (the paper's claim of fifth order in smooth regions)."""
+    ns = [40, 80, 160, 320]
+    e1, einf = zip(*[_advect(orc, n) for n in ns])
+    o1, oinf = _orders(np.array(e1)), _orders(np.array(einf))
+    assert o1[-1] > 4.9 and oinf[-1] > 4.9, (o1, oinf)
+    assert o1[0] > 4.5 and oinf[0] > 4.5, (o1, oinf)
+
+
+@pytest.mark.slow
+def test_advection_jiang_shu_negative_control(orc):
+    """Negative control for the harness above: WENO-JS weights (eq:5, eps = 1e-6) lose
+    order at the critical points of the same solution, so the test can tell schemes apart."""
+    prm = orc.params(scheme=orc.ORC_JS, eps=1e-6)
+    ns = [80, 160]
+    einf = [_advect(orc, n, prm=prm)[1] for n in ns]
+    assert _orders(np.array(einf))[0] < 4.5
+
+
+def test_rk3_temporal_order(orc):
+    """At fixed space grid, halving dt shrinks the time error of TVD-RK3 by 8: the ratio of
+    successive differences of the solution is 2^3 (pins the stage coefficients)."""
+    n = 64
+    u0, dx = I.advection_smooth(n)
+    T = 0.5
+    sols = []
+    for nsteps in (50, 100, 200):
+        u, _, _ = orc.rk3_run_1d(u0, dx, nsteps, dt=T / nsteps, sys=orc.SYS_ADV,
+                                 bc=orc.BC_PERIODIC)
+        sols.append(u[0])
+    d1 = np.max(np.abs(sols[0] - sols[1]))
+    d2 = np.max(np.abs(sols[1] - sols[2]))
+    assert 7.5 < d1 / d2 < 8.5, d1 / d2
+
+
+def test_cfl_time_step_1d(orc):
+    """dt = sigma dx / max_i(|u_i| + c_i) from U^n (Sec. 4.3)."""
+    u, dx = I.shu_osher_like(256)
+    _, dt, _ = orc.rk3_step_1d(u, dx, cfl=0.5)
+    rho, m, E = u
+    vel = m / rho
+    p = 0.4 * (E - 0.5 * rho * vel * vel)
+    smax = np.max(np.abs(vel) + np.sqrt(1.4 * p / rho))
+    assert dt == pytest.approx(0.5 * dx / smax, rel=1e-14)
+    # left state of the Shu-Osher-like data: max(|u|+c) = 4.5660 (to 4 digits)
+    assert smax == pytest.approx(4.5660, abs=1e-4)
+
+
+@pytest.mark.slow
+def test_euler_density_wave_fifth_order(orc):
+    """A density wave rho = 1 + 0.2 sin(pi (x - t)), u = 1, p = 1 is an exact periodic
+    solution of the Euler equations (Sec. 4.3); its error converges at fifth order (pins
+    the flux, the equation of state and the component-wise LF split)."""
+    T = 0.25
+    errs = []
+    for n in (40, 80, 160):
+        u0, dx = I.density_wave_1d(n)
+        dt0 = 0.5 * dx**(5.0 / 3.0) / 2.2
+        nsteps = int(np.ceil(T / dt0))
+        u, _, _ = orc.rk3_run_1d(u0, dx, nsteps, dt=T / nsteps, bc=orc.BC_PERIODIC)
+        ex, _ = I.density_wave_1d(n, t=T)
+        errs.append(np.max(np.abs(u - ex)))
+    o = _orders(np.array(errs))
+    assert o[-1] > 4.7, (errs, o)
+
+
+@pytest.mark.slow
+def test_euler_2d_density_wave_fifth_order(orc):
+    """Dimension-by-dimension 2D Euler (Sec. 4.4, eq:2d) on a diagonal density wave:
+    fifth-order convergence to the exact solution."""
+    T = 0.1
+    errs = []
+    for n in (16, 32, 64):
+        u0, dx, dy = I.density_wave_2d(n, n)
+        dt0 = 0.5 * dx**(5.0 / 3.0) / 3.0
+        nsteps = int(np.ceil(T / dt0))
+        u, _ = orc.rk3_run_2d(u0, dx, dy, nsteps, dt=T / nsteps, bcx=orc.BC_PERIODIC,
+                              bcy=orc.BC_PERIODIC)
+        ex, _, _ = I.density_wave_2d(n, n, t=T)
+        errs.append(np.max(np.abs(u - ex)))
+    o = _orders(np.array(errs))
+    assert o[-1] > 4.5, (errs, o)
+
+
+def test_conservation_periodic(orc):
+    """Periodic: sum_i L_i = 0 by telescoping of eq:2, to rounding."""
+    u = I.random_smooth_1d(257, seed=11)
+    L, _ = orc.rhs_1d(u, 0.01, bc=orc.BC_PERIODIC)
+    for c in range(3):
+        assert abs(L[c].sum()) <= 1e-13 * np.abs(L[c]).sum()
+
+
+def test_conservation_transmissive_edge_flux(orc):
+    """Transmissive: sum_i L_i dx = -(fhat_{N-1/2} - fhat_{-1/2}); when the state is
+    constant over the last six cells at each edge, the edge fluxes equal F(U_edge)
+    (ghost cells are copies), so the sum is -(F(U_{N-1}) - F(U_0))."""
+    n = 200
+    u = I.random_smooth_1d(n, seed=12)
+    u[:, :6] = u[:, :1]
+    u[:, -6:] = u[:, -1:]
+    dx = 0.01
+    L, _ = orc.rhs_1d(u, dx, bc=orc.BC_TRANSMISSIVE)
+
+    def flux(U):
+        rho, m, E = U
+        v = m / rho
+        p = 0.4 * (E - 0.5 * rho * v * v)
+        return np.array([m, m * v + p, v * (E + p)])
+
+    expect = -(flux(u[:, -1]) - flux(u[:, 0]))
+    np.testing.assert_allclose(L.sum(axis=1) * dx, expect, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("s", [1e-2, 1e2])
+def test_self_similarity(orc, s):
+    """Scaling the unknown by s scales L by s (Sec. 2.3 and Sec. 4.2, case 1): no
+    dimensional constant enters the weights except eps = 1e-40, negligible here.  The
+    same check fails with eps = 1e-6 for s = 1e-2, so it has teeth."""
+    n = 200
+    x, dx = I.cell_centres(-1.0, 1.0, n)
+    u = np.stack([np.where(np.abs(x) < 0.3, 1.0, 0.0) + 0.5 * np.sin(3 * np.pi * x)])
+    L1, _ = orc.rhs_1d(u, dx, sys=orc.SYS_ADV, bc=orc.BC_PERIODIC)
+    Ls, _ = orc.rhs_1d(s * u, dx, sys=orc.SYS_ADV, bc=orc.BC_PERIODIC)
+    np.testing.assert_allclose(Ls, s * L1, rtol=0, atol=1e-13 * s * np.abs(L1).max())
+    # Euler: scale rho and p by s at fixed velocity; alpha is unchanged
+    U = I.random_smooth_1d(n, seed=13)
+    Le, _ = orc.rhs_1d(U, dx, bc=orc.BC_PERIODIC)
+    Les, _ = orc.rhs_1d(s * U, dx, bc=orc.BC_PERIODIC)
+    np.testing.assert_allclose(Les, s * Le, rtol=0, atol=1e-12 * s * np.abs(Le).max())
+    if s < 1:
+        prm = orc.params(eps=1e-6)
+        a, _ = orc.rhs_1d(u, dx, sys=orc.SYS_ADV, bc=orc.BC_PERIODIC, prm=prm)
+        b, _ = orc.rhs_1d(s * u, dx, sys=orc.SYS_ADV, bc=orc.BC_PERIODIC, prm=prm)
+        assert np.abs(b - s * a).max() > 1e-8 * s * np.abs(a).max()
+
+
+def test_mirror_symmetry_advection(orc):
+    """Reflecting x and the speed (a -> -a) reflects L exactly: this pins the rule that
+    fhat^- is the reconstruction of f^- mirrored about x_{i+1/2} (Sec. 2)."""
+    n = 101
+    u = I.rng_uniform((1, n), seed=21)
+    L, _ = orc.rhs_1d(u, 0.02, sys=orc.SYS_ADV, bc=orc.BC_PERIODIC, a=1.0)
+    Lr, _ = orc.rhs_1d(u[:, ::-1], 0.02, sys=orc.SYS_ADV, bc=orc.BC_PERIODIC, a=-1.0)
+    np.testing.assert_array_equal(Lr[:, ::-1], L)
+
+
+def test_mirror_symmetry_euler(orc):
+    """Reflect x and negate the momentum: L reflects with its momentum component negated,
+    bit for bit, with transmissive boundaries."""
+    n = 150
+    u = I.random_smooth_1d(n, seed=22)
+    ur = u[:, ::-1].copy()
+    ur[1] *= -1
+    L, _ = orc.rhs_1d(u, 0.01, bc=orc.BC_TRANSMISSIVE)
+    Lr, _ = orc.rhs_1d(ur, 0.01, bc=orc.BC_TRANSMISSIVE)
+    Lr = Lr[:, ::-1].copy()
+    Lr[1] *= -1
+    np.testing.assert_array_equal(Lr, L)
+
+
+def test_step_stays_non_oscillatory(orc):
+    """Advecting the jump of eq:single once around the periodic domain (N = 200, T = 2,
+    CFL 0.5) stays free of spurious oscillation: overshoot and undershoot at most 1 % of
+    the unit jump (the paper shows this only in figures; the threshold is ours)."""
+    n = 200
+    x, dx = I.cell_centres(-1.0, 1.0, n)
+    u0 = I.single_jump(x)[None, :]
+    nsteps = int(round(2.0 / (0.5 * dx)))
+    u, _, _ = orc.rk3_run_1d(u0, dx, nsteps, dt=2.0 / nsteps, sys=orc.SYS_ADV,
+                             bc=orc.BC_PERIODIC)
+    assert u.max() <= u0.max() + 0.01 and u.min() >= u0.min() - 0.01
+
+
+def test_2d_reduces_to_1d(orc):
+    """Data varying only in x with v = 0: the 2D dimension-by-dimension RHS equals the 1D
+    Euler RHS in (rho, rho u, E) and is zero in rho v (Sec. 4.4 vs Sec. 4.3)."""
+    nx, ny = 64, 8
+    U1 = I.random_smooth_1d(nx, seed=31)
+    U2 = np.zeros((4, ny, nx))
+    U2[0] = U1[0]; U2[1] = U1[1]; U2[3] = U1[2]
+    L1, a1 = orc.rhs_1d(U1, 0.01, bc=orc.BC_TRANSMISSIVE)
+    L2, (ax, _) = orc.rhs_2d(U2, 0.01, 0.02)
+    assert ax == pytest.approx(a1, rel=1e-15)
+    for j in range(ny):
+        for c2, c1 in ((0, 0), (1, 1), (3, 2)):
+            np.testing.assert_allclose(L2[c2, j], L1[c1], rtol=0,
+                                       atol=1e-12 * np.abs(L1[c1]).max())
+    assert np.abs(L2[2]).max() == 0.0
+
+
+def test_2d_transpose_symmetry(orc):
+    """Swapping x <-> y and u <-> v transposes L with its momenta swapped."""
+    n = 40
+    U = I.random_smooth_2d(n, n, seed=32)
+    Ut = np.stack([U[0].T, U[2].T, U[1].T, U[3].T])
+    L, _ = orc.rhs_2d(U, 0.01, 0.01, bcx=orc.BC_PERIODIC, bcy=orc.BC_TRANSMISSIVE)
+    Lt, _ = orc.rhs_2d(Ut, 0.01, 0.01, bcx=orc.BC_TRANSMISSIVE, bcy=orc.BC_PERIODIC)
+    back = np.stack([Lt[0].T, Lt[2].T, Lt[1].T, Lt[3].T])
+    for c in range(4):
+        np.testing.assert_allclose(back[c], L[c], rtol=0, atol=1e-12 * np.abs(L[c]).max())
+
+
+def test_2d_time_step(orc):
+    """dt = sigma dtx dty / (dtx + dty), dtx = dx / max(|u|+c), dty = dy / max(|v|+c)
+    (Sec. 4.4)."""
+    U, dx, dy = I.four_quadrant_random(32, 24, seed=3)
+    _, dts = orc.rk3_run_2d(U, dx, dy, 1, cfl=0.5)
+    rho, mx, my, E = U
+    u, v = mx / rho, my / rho
+    p = 0.4 * (E - 0.5 * rho * (u * u + v * v))
+    c = np.sqrt(1.4 * p / rho)
+    dtx, dty = dx / np.max(np.abs(u) + c), dy / np.max(np.abs(v) + c)
+    assert dts[0] == pytest.approx(0.5 * dtx * dty / (dtx + dty), rel=1e-14)
