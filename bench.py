@@ -1,0 +1,171 @@
+"""Benchmark of the WENO-ZN hot path on one MI355X.
+
+Default workload: 1D Euler, component-wise global Lax-Friedrichs WENO-ZN, N = 2^20 cells on
+[-5, 5] (Shu-Osher-like data), transmissive boundaries, fp64, TVD-RK3 at CFL 0.5.  One
+"step" is one TVD-RK3 step (three fused stage kernels: BC map, flux, LF split, WENO-ZN
+reconstruction of every interface, flux difference, stage combination, and the max wave
+speed for the next stage's alpha / next step's dt).  Inputs are resident in HBM before the
+timed region.  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--graph] [--no-cpu-baseline]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
+FP64_VALU_PEAK_TFLOPS = 78.6   # MI355X fp64 vector (FMA = 2 flop)
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2004_07954_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic(kernel, workload):
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it was taken on
+    the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.md" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    rec = None
+    for line in open(path):
+        if line.startswith("TRAFFIC_JSON "):
+            rec = json.loads(line[len("TRAFFIC_JSON "):])
+    if rec is None or rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(n, budget_s=12.0):
+    """The oracle as it stands, on the host cores, over a bounded sample of the same
+    workload (whole RK3 steps at the full N)."""
+    import numpy as np  # noqa: F401
+    from oracle import binding as orc
+    from paper_2004_07954_amd import inputs as I
+    u, dx = I.shu_osher_like(n)
+    orc.lib()
+    t0 = time.perf_counter()
+    u1, _, _ = orc.rk3_run_1d(u, dx, 1, cfl=0.5)
+    t1 = time.perf_counter() - t0
+    steps = max(1, min(40, int(budget_s / max(t1, 1e-3))))
+    t0 = time.perf_counter()
+    orc.rk3_run_1d(u1, dx, steps, cfl=0.5)
+    el = time.perf_counter() - t0
+    return {"value": n * 3 * steps / el, "unit": "cell-RHS/s", "cores": orc.num_threads(),
+            "kind": "oracle",
+            "sample": "%d TVD-RK3 steps (%d RHS evaluations) of the N=%d 1D Euler workload, "
+                      "%.1f s" % (steps, 3 * steps, n, el)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=1 << 20)
+    ap.add_argument("--graph", action="store_true", help="replay the steps as a HIP graph")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2004_07954_amd import api, inputs as I
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    n, K, W = args.n, args.steps, args.warmup
+    u0, dx = I.shu_osher_like(n)
+    u = torch.tensor(u0, dtype=torch.float64, device=dev)
+    stage = torch.empty((2, 3, n), dtype=torch.float64, device=dev)
+    prm = api.params("euler", bc="transmissive")
+    stream = torch.cuda.current_stream()
+
+    log("warmup", W, "steps, N =", n)
+    if W:
+        api.rk3_run_1d(u, dx, W, cfl=0.5, prm=prm, stage=stage)
+    torch.cuda.synchronize()
+    u.copy_(torch.tensor(u0, dtype=torch.float64, device=dev))
+    torch.cuda.synchronize()
+
+    graph = None
+    if args.graph:
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            api.rk3_run_1d(u, dx, K, cfl=0.5, prm=prm, stage=stage)
+        u.copy_(torch.tensor(u0, dtype=torch.float64, device=dev))
+        torch.cuda.synchronize()
+
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    log("timed", K, "steps", "(graph)" if graph else "(eager)")
+    torch.cuda.synchronize()
+    start.record(stream)
+    if graph is not None:
+        graph.replay()
+    else:
+        api.rk3_run_1d(u, dx, K, cfl=0.5, prm=prm, stage=stage)
+    end.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end)
+    uf = u.cpu().numpy()
+    assert np.isfinite(uf).all() and uf[0].min() > 0, "non-physical state after the run"
+
+    launches = 3 * K
+    kernel_ms = ms / launches  # upper bound of the stage kernel's mean duration
+    # algorithmic HBM bytes per cell: stage 1 reads U, writes U1 (48 B); stages 2 and 3 read
+    # U^(s) and U^n and write (72 B): mean 64 B per cell per stage launch
+    bytes_per_launch = n * (48 + 72 + 72) / 3.0
+    achieved = bytes_per_launch / (kernel_ms * 1e-3) / 1e9
+    value = n * 3 * K / (ms * 1e-3)
+    traffic = committed_traffic("stage1d", "euler1d_n%d" % n)
+    rec = {
+        "metric": "WENO-ZN RHS cell-updates/s (1D Euler, fused TVD-RK3 stages)",
+        "value": value,
+        "unit": "cell-RHS/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": ms / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "euler1d_shu_osher_like", "n_cells": n, "nvar": 3,
+                   "bc": "transmissive", "cfl": 0.5, "eps": 1e-40, "A": 10.0,
+                   "launch": "hip_graph" if graph else "stream", "kernels_per_step": 3},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "kernel": "stage1d_kernel<256,4,3>",
+                     "kernel_ms": kernel_ms},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        rec["cpu_baseline"] = cpu_baseline(n)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

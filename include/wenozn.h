@@ -1,0 +1,116 @@
+/* wenozn.h -- C ABI of libwenozn, the MI355X (gfx950) implementation of the hot path of the
+ * WENO-ZN finite-difference scheme of Shen, Zhang, Li and Peng, "A novel method for
+ * constructing high accurate and robust WENO-Z type scheme" (arXiv 2004.07954).
+ *
+ * What the library computes
+ *   For a conservation law U_t + F(U)_x (+ G(U)_y) = 0 on a uniform grid, the semi-discrete
+ *   right-hand side L(U) = -(Fhat_{i+1/2} - Fhat_{i-1/2})/dx [- (Ghat_{j+1/2} - Ghat_{j-1/2})/dy]
+ *   (Sec. 2, eq:2; Sec. 4.4, eq:2d), where every interface flux is the fifth-order WENO
+ *   reconstruction (eq:3, eq:4) of the Lax-Friedrichs split flux f^{+-} = (F +- alpha U)/2,
+ *   component by component, with the Jiang-Shu indicators IS_k (eq:isjiang), the global
+ *   indicators tau5 = |IS0 - IS2| (eq:tau) and tau8 (eq:tau8), the adaptive function
+ *   C = A ((IS0 + IS2 - tau5 + eps)/(tau5 + eps))^2 (eq:function) and the WENO-ZN weights
+ *   alpha_k = c_k (C + tau8/(IS_k + eps)) (eq:new).  f^- is reconstructed from the five points
+ *   mirrored about x_{i+1/2} (Sec. 2).  Time integration is the three-stage TVD Runge-Kutta
+ *   scheme the paper cites (Sec. 4) with dt = cfl dx / max(|u| + c) from U^n (Sec. 4.3) or
+ *   dt = cfl dtx dty / (dtx + dty) in 2D (Sec. 4.4).
+ *
+ * Conventions shared by every entry point
+ *   - Every array argument is a DEVICE pointer owned by the caller; the library never
+ *     allocates, frees or synchronises.  All work is enqueued on `stream` (a hipStream_t;
+ *     NULL = the default stream) and is asynchronous with respect to the host.
+ *   - States are structure-of-arrays fp64: 1D [nvar][n] (nvar = 1 advection, 3 Euler:
+ *     rho, rho u, E); 2D [4][ny][nx] with x fastest (rho, rho u, rho v, E).
+ *     No ghost cells are stored: the boundary conditions are applied inside the kernels.
+ *   - `ws` is a device workspace of at least wzn_workspace_bytes() bytes, 256-byte aligned,
+ *     holding the reduction slots of the global Lax-Friedrichs alpha and dt.  Calls that
+ *     share one `ws` must be ordered on one stream.
+ *   - Arguments are validated before anything is enqueued; on error nothing is enqueued and
+ *     a status code is returned (wzn_last_error() then describes it).  No C++ exception
+ *     crosses the ABI.  A failed launch returns WZN_ERR_HIP.
+ */
+#ifndef WENOZN_H
+#define WENOZN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define WZN_ABI_VERSION 1
+
+enum {
+  WZN_OK = 0,
+  WZN_ERR_ARG = 1,        /* null pointer, bad parameter value */
+  WZN_ERR_SIZE = 2,       /* grid too small (n, nx, ny must be >= 6) or too large */
+  WZN_ERR_DTYPE = 3,      /* unsupported dtype for this entry point */
+  WZN_ERR_HIP = 4,        /* a HIP runtime call or kernel launch failed */
+  WZN_ERR_UNSUPPORTED = 6 /* parameter combination not implemented on the GPU */
+};
+
+enum { WZN_ADVECTION = 0, WZN_EULER = 1 };          /* system */
+enum { WZN_FP64 = 0, WZN_FP32 = 1 };               /* dtype */
+enum { WZN_PERIODIC = 0, WZN_TRANSMISSIVE = 1 };   /* boundary condition per direction */
+
+typedef struct {
+  uint32_t abi_version; /* must equal WZN_ABI_VERSION */
+  int32_t system;       /* WZN_ADVECTION (1D only) or WZN_EULER */
+  int32_t dtype;        /* WZN_FP64 (all entry points) or WZN_FP32 (2D only) */
+  int32_t bc_x, bc_y;   /* WZN_PERIODIC or WZN_TRANSMISSIVE; transmissive copies the edge
+                           cell into the three ghost cells */
+  int32_t p_C;          /* exponent of the ratio inside C (eq:function): must be 2 */
+  int32_t q;            /* exponent on tau8/(IS_k+eps) (eq:new): must be 1 */
+  int32_t reserved;
+  double adv_speed;     /* a of u_t + a u_x = 0 (advection only) */
+  double gamma;         /* ratio of specific heats, Sec. 4.3: 1.4 */
+  double A;             /* constant of eq:function: 10 */
+  double eps;           /* epsilon of the weights: 1e-40 (fp64) */
+  double lf_alpha_x;    /* < 0: alpha_x = max(|u| + c) of each RHS input (Euler) or |a|
+                           (advection); >= 0: this frozen value */
+  double lf_alpha_y;    /* same for the y direction (2D) */
+} wzn_params;
+
+/* Fill *p with the paper's values for `system`: A = 10, eps = 1e-40, p_C = 2, q = 1,
+ * gamma = 1.4, a = 1, fp64, transmissive (Euler) or periodic (advection), alphas reduced. */
+void wzn_default_params(wzn_params* p, int32_t system);
+
+int32_t wzn_abi_version(void);
+const char* wzn_status_string(int32_t status);
+/* Message of the last failing call on this host thread ("" if none). */
+const char* wzn_last_error(void);
+
+/* Bytes of device workspace `ws` needed by any entry point for grids up to nx * ny cells
+ * (ny = 1 in 1D).  Currently a small constant. */
+size_t wzn_workspace_bytes(const wzn_params* p, int64_t nx, int64_t ny);
+
+/* ---------------------------------------------------------------- 1D
+ * wzn_rhs_1d: dudt = L(u) (eq:2) for one state u[nvar][n].  u and dudt must not alias.
+ * The LF alpha is p->lf_alpha_x if >= 0, else max over cells of |u| + c (Euler) or |a|. */
+int32_t wzn_rhs_1d(const wzn_params* p, const void* u, void* dudt, int64_t n, double dx,
+                   void* ws, void* stream);
+
+/* wzn_rk3_run_1d: advance u[nvar][n] in place by `nsteps` TVD-RK3 steps.
+ *   stage   device scratch of 2 * nvar * n elements (the intermediate stage states).
+ *   dt_in   NULL: dt = cfl dx / max(|u| + c) of U^n (Sec. 4.3; |a| for advection);
+ *           else device array [nsteps] of step sizes.
+ *   alpha_in NULL: LF alpha from p->lf_alpha_x (reduced per stage if < 0);
+ *           else device array [3 * nsteps] of frozen per-stage alphas.
+ *   dt_out, alpha_out  NULL or device arrays [nsteps] / [3 * nsteps] receiving the dt of
+ *           every step and the alpha of every stage.
+ * The whole run is enqueued as 1 + 3 * nsteps kernels with no host synchronisation, so it
+ * can be captured in a HIP graph. */
+int32_t wzn_rk3_run_1d(const wzn_params* p, void* u, void* stage, int64_t n, double dx,
+                       double cfl, int32_t nsteps, const double* dt_in, const double* alpha_in,
+                       double* dt_out, double* alpha_out, void* ws, void* stream);
+
+/* wzn_rk3_step_1d: one step; same as wzn_rk3_run_1d with nsteps = 1. */
+int32_t wzn_rk3_step_1d(const wzn_params* p, void* u, void* stage, int64_t n, double dx,
+                        double cfl, const double* dt_in, double* dt_out, void* ws,
+                        void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WENOZN_H */

@@ -1,0 +1,139 @@
+"""PyTorch-facing binding of libwenozn: argument marshalling only.
+
+Every function takes device tensors, checks their dtype, layout and device, and calls the
+C ABI of include/wenozn.h on the current torch stream.  All arithmetic of the scheme runs in
+the library's HIP kernels; PyTorch provides device memory and streams.
+"""
+import ctypes as C
+
+import torch
+
+from . import _lib
+from ._lib import WznParams, check, lib
+
+SYSTEMS = {"advection": _lib.WZN_ADVECTION, "euler": _lib.WZN_EULER}
+BCS = {"periodic": _lib.WZN_PERIODIC, "transmissive": _lib.WZN_TRANSMISSIVE}
+
+
+def params(system="euler", bc="transmissive", bc_y=None, adv_speed=1.0, gamma=1.4, A=10.0,
+           eps=1e-40, lf_alpha=None, lf_alpha_y=None, dtype="fp64"):
+    """WENO-ZN parameters; defaults are the paper's (A = 10, eps = 1e-40, gamma = 1.4)."""
+    p = WznParams()
+    lib().wzn_default_params(C.byref(p), SYSTEMS[system])
+    p.bc_x = BCS[bc]
+    p.bc_y = BCS[bc_y or bc]
+    p.adv_speed = adv_speed
+    p.gamma = gamma
+    p.A = A
+    p.eps = eps
+    p.lf_alpha_x = -1.0 if lf_alpha is None else float(lf_alpha)
+    p.lf_alpha_y = -1.0 if lf_alpha_y is None else float(lf_alpha_y)
+    p.dtype = {"fp64": _lib.WZN_FP64, "fp32": _lib.WZN_FP32}[dtype]
+    return p
+
+
+_WS = {}
+
+
+def workspace(device=None):
+    """The per-device workspace tensor (allocated once, reused by every call)."""
+    dev = torch.device(device or "cuda")
+    if dev.index is None:
+        dev = torch.device("cuda", torch.cuda.current_device())
+    ws = _WS.get(dev.index)
+    if ws is None:
+        nbytes = lib().wzn_workspace_bytes(None, 1, 1)
+        ws = torch.zeros(nbytes, dtype=torch.uint8, device=dev)
+        assert ws.data_ptr() % 256 == 0
+        _WS[dev.index] = ws
+    return ws
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _check_state(u, nv, name="u", dtype=torch.float64):
+    if not isinstance(u, torch.Tensor) or not u.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+    if u.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, u.dtype))
+    if not u.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if u.dim() != 2 or u.shape[0] != nv:
+        raise ValueError("%s must have shape [%d, n], got %s" % (name, nv, tuple(u.shape)))
+
+
+def _nv(p):
+    return 1 if p.system == _lib.WZN_ADVECTION else 3
+
+
+def _dev_f64(x, n, name, device):
+    if x is None:
+        return None
+    if not isinstance(x, torch.Tensor):
+        x = torch.as_tensor(x, dtype=torch.float64)
+    x = x.to(device=device, dtype=torch.float64).reshape(-1).contiguous()
+    if x.numel() != n:
+        raise ValueError("%s must have %d entries" % (name, n))
+    return x
+
+
+def rhs_1d(u, dx, prm=None, out=None):
+    """L(u) for u[nvar, n] (nvar = 1 advection, 3 Euler)."""
+    prm = prm or params()
+    _check_state(u, _nv(prm))
+    out = torch.empty_like(u) if out is None else out
+    _check_state(out, _nv(prm), "out")
+    check(lib().wzn_rhs_1d(C.byref(prm), _ptr(u), _ptr(out), u.shape[1], float(dx),
+                           _ptr(workspace(u.device)), _stream()))
+    return out
+
+
+def rk3_run_1d(u, dx, nsteps, cfl=0.5, prm=None, dt=None, alpha=None, stage=None, record=False):
+    """Advance u[nvar, n] in place by nsteps TVD-RK3 steps.
+
+    dt: None (CFL from U^n) or [nsteps] step sizes; alpha: None or [nsteps, 3] frozen LF
+    alphas.  With record=True returns (dt_history[nsteps], alpha_history[nsteps, 3]) as
+    device tensors."""
+    prm = prm or params()
+    _check_state(u, _nv(prm))
+    n = u.shape[1]
+    if stage is None:
+        stage = torch.empty((2,) + tuple(u.shape), dtype=u.dtype, device=u.device)
+    if stage.numel() < 2 * u.numel() or not stage.is_contiguous() or stage.dtype != u.dtype:
+        raise ValueError("stage must be a contiguous fp64 tensor of 2 * u.numel() elements")
+    if dt is None:
+        dt_t = None
+    elif isinstance(dt, (int, float)):
+        dt_t = torch.full((nsteps,), float(dt), dtype=torch.float64, device=u.device)
+    else:
+        dt_t = _dev_f64(dt, nsteps, "dt", u.device)
+    al_t = _dev_f64(alpha, 3 * nsteps, "alpha", u.device)
+    dt_o = torch.empty(nsteps, dtype=torch.float64, device=u.device) if record else None
+    al_o = torch.empty(3 * nsteps, dtype=torch.float64, device=u.device) if record else None
+    check(lib().wzn_rk3_run_1d(C.byref(prm), _ptr(u), _ptr(stage), n, float(dx), float(cfl),
+                               int(nsteps), _ptr(dt_t), _ptr(al_t), _ptr(dt_o), _ptr(al_o),
+                               _ptr(workspace(u.device)), _stream()))
+    if record:
+        return dt_o, al_o.view(nsteps, 3)
+    return None
+
+
+def rk3_step_1d(u, dx, cfl=0.5, prm=None, dt=None, stage=None):
+    """One TVD-RK3 step in place; returns the dt used (device tensor of 1 element)."""
+    prm = prm or params()
+    _check_state(u, _nv(prm))
+    if stage is None:
+        stage = torch.empty((2,) + tuple(u.shape), dtype=u.dtype, device=u.device)
+    dt_t = None if dt is None else torch.full((1,), float(dt), dtype=torch.float64,
+                                              device=u.device)
+    dt_o = torch.empty(1, dtype=torch.float64, device=u.device)
+    check(lib().wzn_rk3_step_1d(C.byref(prm), _ptr(u), _ptr(stage), u.shape[1], float(dx),
+                                float(cfl), _ptr(dt_t), _ptr(dt_o), _ptr(workspace(u.device)),
+                                _stream()))
+    return dt_o

@@ -1,0 +1,154 @@
+// extern "C" entry points of libwenozn: argument validation, error reporting and dispatch to
+// the kernels.  Declarations and the meaning of every argument are in include/wenozn.h.
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "wzn_host.hpp"
+
+namespace wzn {
+
+static thread_local char g_err[512] = "";
+
+int set_error(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+int check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_error(WZN_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+  return WZN_OK;
+}
+
+__global__ void fill_double_kernel(double* p, double v) {
+  if (threadIdx.x == 0) p[0] = v;
+}
+
+int launch_fill_double(double* p, double v, hipStream_t s) {
+  hipLaunchKernelGGL(fill_double_kernel, dim3(1), dim3(64), 0, s, p, v);
+  return check_launch("fill_double_kernel");
+}
+
+static Tuning1D g_tune_euler = {256, 4};
+
+Tuning1D tuning_1d(int nv, int64_t n) {
+  (void)n;
+  if (nv == 1) return Tuning1D{64, 4};
+  return g_tune_euler;
+}
+
+static int check_params(const wzn_params* p, bool allow_fp32) {
+  if (!p) return set_error(WZN_ERR_ARG, "params is NULL");
+  if (p->abi_version != WZN_ABI_VERSION)
+    return set_error(WZN_ERR_ARG, "abi_version %u != %d", p->abi_version, WZN_ABI_VERSION);
+  if (p->system != WZN_ADVECTION && p->system != WZN_EULER)
+    return set_error(WZN_ERR_ARG, "unknown system %d", p->system);
+  if (p->dtype != WZN_FP64 && !(allow_fp32 && p->dtype == WZN_FP32))
+    return set_error(WZN_ERR_DTYPE, "dtype %d not supported here", p->dtype);
+  if (p->bc_x != WZN_PERIODIC && p->bc_x != WZN_TRANSMISSIVE)
+    return set_error(WZN_ERR_ARG, "unknown bc_x %d", p->bc_x);
+  if (p->bc_y != WZN_PERIODIC && p->bc_y != WZN_TRANSMISSIVE)
+    return set_error(WZN_ERR_ARG, "unknown bc_y %d", p->bc_y);
+  if (p->p_C != 2 || p->q != 1)
+    return set_error(WZN_ERR_UNSUPPORTED, "only p_C = 2, q = 1 (the paper's weights) run here");
+  if (!(p->eps > 0.0) || !(p->A > 0.0))
+    return set_error(WZN_ERR_ARG, "eps and A must be positive");
+  if (p->system == WZN_EULER && !(p->gamma > 1.0))
+    return set_error(WZN_ERR_ARG, "gamma must exceed 1");
+  if (p->system == WZN_ADVECTION && !(p->adv_speed != 0.0) && p->lf_alpha_x < 0.0)
+    return set_error(WZN_ERR_ARG, "advection speed must be nonzero");
+  return WZN_OK;
+}
+
+static int check_1d(const wzn_params* p, int64_t n, double dx, void* ws) {
+  int st = check_params(p, false);
+  if (st) return st;
+  if (n < 6) return set_error(WZN_ERR_SIZE, "n = %lld < 6", (long long)n);
+  if (n > (int64_t)1 << 40) return set_error(WZN_ERR_SIZE, "n = %lld too large", (long long)n);
+  if (!(dx > 0.0)) return set_error(WZN_ERR_ARG, "dx must be positive");
+  if (!ws) return set_error(WZN_ERR_ARG, "workspace is NULL");
+  if (((uintptr_t)ws) & 255) return set_error(WZN_ERR_ARG, "workspace not 256-byte aligned");
+  return WZN_OK;
+}
+
+}  // namespace wzn
+
+using namespace wzn;
+
+extern "C" {
+
+void wzn_default_params(wzn_params* p, int32_t system) {
+  if (!p) return;
+  memset(p, 0, sizeof(*p));
+  p->abi_version = WZN_ABI_VERSION;
+  p->system = system;
+  p->dtype = WZN_FP64;
+  p->bc_x = p->bc_y = system == WZN_ADVECTION ? WZN_PERIODIC : WZN_TRANSMISSIVE;
+  p->p_C = 2;
+  p->q = 1;
+  p->adv_speed = 1.0;
+  p->gamma = 1.4;
+  p->A = 10.0;
+  p->eps = 1e-40;
+  p->lf_alpha_x = -1.0;
+  p->lf_alpha_y = -1.0;
+}
+
+int32_t wzn_abi_version(void) { return WZN_ABI_VERSION; }
+
+const char* wzn_status_string(int32_t status) {
+  switch (status) {
+    case WZN_OK: return "ok";
+    case WZN_ERR_ARG: return "invalid argument";
+    case WZN_ERR_SIZE: return "invalid size";
+    case WZN_ERR_DTYPE: return "unsupported dtype";
+    case WZN_ERR_HIP: return "HIP error";
+    case WZN_ERR_UNSUPPORTED: return "unsupported parameters";
+    default: return "unknown status";
+  }
+}
+
+const char* wzn_last_error(void) { return g_err; }
+
+size_t wzn_workspace_bytes(const wzn_params* p, int64_t nx, int64_t ny) {
+  (void)p; (void)nx; (void)ny;
+  return sizeof(unsigned long long) * WS_WORDS;
+}
+
+int32_t wzn_rhs_1d(const wzn_params* p, const void* u, void* dudt, int64_t n, double dx,
+                   void* ws, void* stream) {
+  g_err[0] = 0;
+  int st = check_1d(p, n, dx, ws);
+  if (st) return st;
+  if (!u || !dudt) return set_error(WZN_ERR_ARG, "u or dudt is NULL");
+  if (u == dudt) return set_error(WZN_ERR_ARG, "u and dudt must not alias");
+  Workspace w = make_workspace(ws);
+  return rhs_1d(p, (const double*)u, (double*)dudt, n, dx, &w, (hipStream_t)stream);
+}
+
+int32_t wzn_rk3_run_1d(const wzn_params* p, void* u, void* stage, int64_t n, double dx,
+                       double cfl, int32_t nsteps, const double* dt_in, const double* alpha_in,
+                       double* dt_out, double* alpha_out, void* ws, void* stream) {
+  g_err[0] = 0;
+  int st = check_1d(p, n, dx, ws);
+  if (st) return st;
+  if (!u || !stage) return set_error(WZN_ERR_ARG, "u or stage is NULL");
+  if (nsteps < 0) return set_error(WZN_ERR_ARG, "nsteps < 0");
+  if (!dt_in && !(cfl > 0.0)) return set_error(WZN_ERR_ARG, "cfl must be positive");
+  Workspace w = make_workspace(ws);
+  return rk3_run_1d(p, (double*)u, (double*)stage, n, dx, cfl, nsteps, dt_in, alpha_in, dt_out,
+                    alpha_out, &w, (hipStream_t)stream);
+}
+
+int32_t wzn_rk3_step_1d(const wzn_params* p, void* u, void* stage, int64_t n, double dx,
+                        double cfl, const double* dt_in, double* dt_out, void* ws,
+                        void* stream) {
+  return wzn_rk3_run_1d(p, u, stage, n, dx, cfl, 1, dt_in, nullptr, dt_out, nullptr, ws, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,130 @@
+// Device building blocks of the WENO-ZN hot path for gfx950 (fp64).
+//
+// The reconstruction is evaluated on a sliding window of K + 4 consecutive values held in
+// registers, producing K consecutive interface fluxes.  Differences shared by neighbouring
+// interfaces are computed once per window:
+//   g_j = v_{j+1} - v_j,   D_j = g_{j+1} - g_j   (second difference centred at v_{j+1})
+// and the Jiang-Shu indicators (Sec. 2.1, eq:isjiang) of interface m of the window,
+// stencil (a..e) = (v_m .. v_{m+4}), are
+//   IS0 = 13/12 D_m^2     + 1/4 (3 g_{m+1} - g_m)^2
+//   IS1 = 13/12 D_{m+1}^2 + 1/4 (g_{m+1} + g_{m+2})^2
+//   IS2 = 13/12 D_{m+2}^2 + 1/4 (g_{m+3} - 3 g_{m+2})^2
+// tau8 = (D_m - 2 D_{m+1} + D_{m+2})^2 (Sec. 3, eq:tau8).  The same 13/12 D_j^2 term serves
+// the three indicators centred at v_{j+1}.
+//
+// All indicators are carried scaled by 4 (the exact power-of-two factor only moves the
+// exponent): IS' = 4 IS, tau' = 4 tau, with eps' = 4 eps, so every ratio the weights use is
+// unchanged.  The caller additionally reconstructs w = 2 f (the split flux without its 1/2),
+// which scales IS by 4 again and the flux by 2; the caller passes eps_s = 16 eps and halves
+// the flux difference.
+//
+// Weights (Sec. 3, eq:function and eq:new, normalised as eq:5) are evaluated in the
+// algebraically equal single-divide form: with s_k = IS_k + eps, num = IS0 + IS2 - tau5 + eps,
+// den = tau5 + eps,
+//   alpha_k * den^2 * s0 s1 s2 = c_k * prod_{j != k} s_j * (A num^2 s_k + tau8 den^2) =: c_k B_k
+// and, since sum_k omega_k = 1,
+//   fhat = q1 + (c0 B0 (q0 - q1) + c2 B2 (q2 - q1)) / sum_k c_k B_k
+// with q0 - q1 = (D_m - D_{m+1})/3, q2 - q1 = (D_{m+1} - D_{m+2})/6 and
+// q1 = (v_{m+2} + v_{m+3})/2 - D_{m+1}/6 (eq:4 rewritten with differences).
+// Every term is >= eps^5 ~ 1e-200 for eps = 1e-40 (fp64 safe) and < 1e300 for
+// |w| < ~1e30.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wzn {
+
+// 1/x with one v_rcp_f64 and Newton steps; relative error ~1 ulp for normal x.
+__device__ __forceinline__ double fast_div(double num, double den) {
+  double r = __builtin_amdgcn_rcp(den);
+  double e = __builtin_fma(-den, r, 1.0);
+  r = __builtin_fma(e, r, r);
+  e = __builtin_fma(-den, r, 1.0);
+  r = __builtin_fma(e, r, r);
+  double q = num * r;
+  double res = __builtin_fma(-den, q, num);
+  return __builtin_fma(res, r, q);
+}
+
+// K consecutive WENO-ZN interface values from a window v[0 .. K+3].
+// Interface m uses stencil v[m .. m+4] and returns fhat_{m} (the value at the interface
+// between v[m+2] and v[m+3]).
+template <int K>
+__device__ __forceinline__ void wzn_window(const double* v, double* fh, double eps_s,
+                                           double A) {
+  constexpr int NG = K + 3;
+  constexpr int ND = K + 2;
+  double g[NG];
+#pragma unroll
+  for (int j = 0; j < NG; ++j) g[j] = v[j + 1] - v[j];
+  double D[ND];
+#pragma unroll
+  for (int j = 0; j < ND; ++j) D[j] = g[j + 1] - g[j];
+  // per-centre 13/3 D^2 (indicators scaled by 4)
+  double DD[ND];
+#pragma unroll
+  for (int j = 0; j < ND; ++j) DD[j] = (D[j] * (13.0 / 3.0)) * D[j];
+
+#pragma unroll
+  for (int m = 0; m < K; ++m) {
+    const double E0 = __builtin_fma(3.0, g[m + 1], -g[m]);
+    const double E1 = g[m + 1] + g[m + 2];
+    const double E2 = __builtin_fma(-3.0, g[m + 2], g[m + 3]);
+    const double IS0 = __builtin_fma(E0, E0, DD[m]);
+    const double IS1 = __builtin_fma(E1, E1, DD[m + 1]);
+    const double IS2 = __builtin_fma(E2, E2, DD[m + 2]);
+
+    const double d = IS0 - IS2;
+    const double t5 = __builtin_fabs(d);
+    const double num = ((IS0 + IS2) - t5) + eps_s;
+    const double den = t5 + eps_s;
+    const double s0 = IS0 + eps_s, s1 = IS1 + eps_s, s2 = IS2 + eps_s;
+    // 4 tau8 = (2 (D_m - 2 D_{m+1} + D_{m+2}))^2 ; H = 4 tau8 den^2
+    const double b = __builtin_fma(-2.0, D[m + 1], D[m] + D[m + 2]);
+    const double bd = (b + b) * den;
+    const double H = bd * bd;
+    const double G = (A * num) * num;
+    const double t0 = __builtin_fma(G, s0, H);
+    const double t1 = __builtin_fma(G, s1, H);
+    const double t2 = __builtin_fma(G, s2, H);
+    const double B0 = (s1 * s2) * t0;
+    const double B1 = (s0 * s2) * t1;
+    const double B2 = (s0 * s1) * t2;
+    const double S = __builtin_fma(0.1, B0, __builtin_fma(0.6, B1, 0.3 * B2));
+    const double x0 = (D[m] - D[m + 1]) * (0.1 / 3.0);
+    const double x2 = (D[m + 1] - D[m + 2]) * (0.3 / 6.0);
+    const double nr = __builtin_fma(B0, x0, B2 * x2);
+    const double base = __builtin_fma(-1.0 / 6.0, D[m + 1], 0.5 * (v[m + 2] + v[m + 3]));
+    fh[m] = base + fast_div(nr, S);
+  }
+}
+
+// Index map of the boundary conditions for a global cell index g in [-3, n + 2]
+// (and harmlessly clamped beyond): periodic wrap or transmissive copy of the edge cell.
+__device__ __forceinline__ int64_t bc_index(int64_t g, int64_t n, int bc) {
+  if (bc == 0) {  // periodic
+    if (g < 0) g += n;
+    else if (g >= n) g -= n;
+    g = g < 0 ? 0 : (g >= n ? n - 1 : g);
+    return g;
+  }
+  return g < 0 ? 0 : (g >= n ? n - 1 : g);
+}
+
+// Max of non-negative doubles through their bit patterns (order preserving; a NaN wins).
+__device__ __forceinline__ void atomic_max_pos(unsigned long long* slot, double v) {
+  atomicMax(slot, (unsigned long long)__double_as_longlong(v));
+}
+
+__device__ __forceinline__ double slot_value(const unsigned long long* slot) {
+  return __longlong_as_double((long long)(*slot));
+}
+
+// Wave-wide max (64 lanes) via cross-lane shuffles.
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+}  // namespace wzn

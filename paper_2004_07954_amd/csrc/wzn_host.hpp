@@ -1,0 +1,50 @@
+// Host-side helpers shared by the translation units of libwenozn: error reporting,
+// workspace layout and launch tuning.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/wenozn.h"
+
+namespace wzn {
+
+// Layout of the caller's device workspace (64-bit words).
+struct Workspace {
+  unsigned long long* speed;    // [3] ring of max(|u|+c) slots (x direction)
+  unsigned long long* speed_y;  // [3] ring of max(|v|+c) slots (y direction)
+  double* dt;                   // [1] dt of the current step
+  unsigned long long* counter;  // [1] work-queue counter (batched launch)
+  unsigned long long* scratch;  // [WS_SCRATCH_WORDS] spare words
+};
+constexpr int WS_WORDS = 512;  // 4 KiB
+constexpr int WS_SCRATCH_WORDS = WS_WORDS - 16;
+
+inline Workspace make_workspace(void* ws) {
+  unsigned long long* w = (unsigned long long*)ws;
+  Workspace s;
+  s.speed = w;
+  s.speed_y = w + 3;
+  s.dt = (double*)(w + 6);
+  s.counter = w + 7;
+  s.scratch = w + 16;
+  return s;
+}
+
+struct Tuning1D {
+  int nt;  // threads per workgroup
+  int k;   // consecutive interfaces per thread
+};
+Tuning1D tuning_1d(int nv, int64_t n);
+
+int set_error(int code, const char* fmt, ...);
+int check_launch(const char* what);
+int launch_zero_words(unsigned long long* p, int count, hipStream_t s);
+int launch_fill_double(double* p, double v, hipStream_t s);
+
+int rhs_1d(const wzn_params* p, const double* u, double* dudt, int64_t n, double dx,
+           Workspace* ws, hipStream_t s);
+int rk3_run_1d(const wzn_params* p, double* u, double* stage, int64_t n, double dx, double cfl,
+               int32_t nsteps, const double* dt_in, const double* alpha_in, double* dt_out,
+               double* alpha_out, Workspace* ws, hipStream_t s);
+
+}  // namespace wzn

@@ -1,0 +1,57 @@
+"""The C ABI library loads and exports every symbol include/wenozn.h declares (no GPU
+needed: nothing here launches a kernel)."""
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "wenozn.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(wzn_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_header_declares_entry_points():
+    syms = declared_symbols()
+    for s in ("wzn_rhs_1d", "wzn_rk3_run_1d", "wzn_rk3_step_1d", "wzn_workspace_bytes"):
+        assert s in syms
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2004_07954_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libwenozn.so not built; run __graft_entry__.build()")
+    L = _lib.lib()
+    for s in declared_symbols():
+        assert hasattr(L, s), s
+    names = {name for name, _, _ in _lib.SIGNATURES}
+    assert set(declared_symbols()) == names
+
+
+def test_host_only_calls():
+    """Entry points that touch no device memory: defaults, status strings, workspace size,
+    and argument validation (rejected before any launch)."""
+    import ctypes as C
+    from paper_2004_07954_amd import _lib
+    L = _lib.lib()
+    p = _lib.WznParams()
+    L.wzn_default_params(C.byref(p), _lib.WZN_EULER)
+    assert p.abi_version == _lib.WZN_ABI_VERSION and p.A == 10.0 and p.eps == 1e-40
+    assert p.p_C == 2 and p.q == 1 and p.gamma == 1.4
+    assert L.wzn_status_string(0) == b"ok"
+    assert L.wzn_workspace_bytes(C.byref(p), 1 << 20, 1) >= 256
+    # n < 6 is rejected before anything is enqueued
+    rc = L.wzn_rhs_1d(C.byref(p), C.c_void_p(256), C.c_void_p(512), 5, 0.1, C.c_void_p(1024),
+                      None)
+    assert rc == _lib.WZN_ERR_SIZE and b"n = 5" in L.wzn_last_error()
+    p.q = 2
+    rc = L.wzn_rhs_1d(C.byref(p), C.c_void_p(256), C.c_void_p(512), 100, 0.1,
+                      C.c_void_p(1024), None)
+    assert rc == _lib.WZN_ERR_UNSUPPORTED
+    p.q = 1
+    rc = L.wzn_rhs_1d(C.byref(p), C.c_void_p(256), C.c_void_p(512), 100, 0.1,
+                      C.c_void_p(1000), None)
+    assert rc == _lib.WZN_ERR_ARG  # unaligned workspace

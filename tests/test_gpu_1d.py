@@ -1,0 +1,216 @@
+"""GPU parity of the 1D HIP path against the CPU oracle (through the C ABI).
+
+Tolerances (normwise per component, the reading of "relative 1e-12 per RHS evaluation and
+1e-10 after the full run"): max_i |x_gpu - x_ref| / max_i |x_ref| <= 1e-12 for one RHS and
+<= 1e-10 after a run.
+"""
+import numpy as np
+import pytest
+
+from paper_2004_07954_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+RHS_TOL = 1e-12
+RUN_TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2004_07954_amd import api
+    return api
+
+
+def note(*args):
+    print("[gpu-case]", *args, flush=True)
+
+
+def normwise(gpu, ref):
+    gpu = np.asarray(gpu)
+    ref = np.asarray(ref)
+    out = []
+    for c in range(ref.shape[0]):
+        scale = np.abs(ref[c]).max()
+        out.append(np.abs(gpu[c] - ref[c]).max() / (scale if scale > 0 else 1.0))
+    return max(out)
+
+
+def to_dev(x):
+    import torch
+    return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+@pytest.mark.parametrize("n", [6, 7, 64, 1022, 1023, 1024, 5000, 20011])
+@pytest.mark.parametrize("bc", ["transmissive", "periodic"])
+def test_rhs_euler_random(api, orc, n, bc):
+    note("rhs_1d euler random", n, bc)
+    u = I.random_smooth_1d(n, seed=100 + n)
+    dx = 1.0 / n
+    g = api.rhs_1d(to_dev(u), dx, api.params("euler", bc=bc)).cpu().numpy()
+    r, _ = orc.rhs_1d(u, dx, bc=orc.BC_TRANSMISSIVE if bc == "transmissive" else orc.BC_PERIODIC)
+    assert normwise(g, r) <= RHS_TOL
+
+
+@pytest.mark.parametrize("n", [200, 4099])
+def test_rhs_shu_osher_like(api, orc, n):
+    """Discontinuous data (shock-tube left state against a sine wave)."""
+    note("rhs_1d shu-osher-like", n)
+    u, dx = I.shu_osher_like(n)
+    g = api.rhs_1d(to_dev(u), dx, api.params("euler")).cpu().numpy()
+    r, _ = orc.rhs_1d(u, dx)
+    assert normwise(g, r) <= RHS_TOL
+
+
+def test_rhs_frozen_alpha(api, orc):
+    note("rhs_1d frozen alpha")
+    n = 3001
+    u = I.random_smooth_1d(n, seed=7)
+    g = api.rhs_1d(to_dev(u), 0.01, api.params("euler", lf_alpha=3.25)).cpu().numpy()
+    r, al = orc.rhs_1d(u, 0.01, alpha=3.25)
+    assert al == 3.25
+    assert normwise(g, r) <= RHS_TOL
+
+
+@pytest.mark.parametrize("n", [200, 1500])
+def test_rhs_advection(api, orc, n):
+    note("rhs_1d advection", n)
+    u, dx = I.advection_smooth(n)
+    u = u + 0.3 * (np.abs(I.cell_centres(-1, 1, n)[0]) < 0.25)
+    for a in (1.0, -0.7):
+        g = api.rhs_1d(to_dev(u), dx, api.params("advection", bc="periodic",
+                                                 adv_speed=a)).cpu().numpy()
+        r, _ = orc.rhs_1d(u, dx, sys=orc.SYS_ADV, bc=orc.BC_PERIODIC, a=a)
+        assert normwise(g, r) <= RHS_TOL
+
+
+def test_rhs_edge_stencils(api, orc):
+    """Constant, integer-linear, integer-cubic, peak and step data, including large
+    amplitudes (the degenerate cases of the weights: IS = 0, tau = 0, C = A)."""
+    n = 64
+    i = np.arange(n, dtype=float)
+    cases = {
+        "const": np.ones(n) * 2.0,
+        "linear": 1.0 + 0.01 * i,
+        "cubic": 1.0 + 1e-6 * (i**3 - 2 * i),
+        "peak": 1.0 + (np.abs(i - 30) <= 1) * 1.0,
+        "step": 1.0 + (i >= 32) * 1.0,
+        "bigstep": 1.0 + (i >= 20) * 1e6,
+    }
+    for name, rho in cases.items():
+        note("edge stencil", name)
+        u = I.prim_to_cons_1d(rho, 0.3, 1.0 + 0.5 * (i >= 40))
+        g = api.rhs_1d(to_dev(u), 0.05, api.params("euler")).cpu().numpy()
+        r, _ = orc.rhs_1d(u, 0.05)
+        assert normwise(g, r) <= RHS_TOL, name
+        ua = rho[None, :] - 1.0
+        g = api.rhs_1d(to_dev(ua), 0.05, api.params("advection", bc="periodic")).cpu().numpy()
+        r, _ = orc.rhs_1d(ua, 0.05, sys=orc.SYS_ADV, bc=orc.BC_PERIODIC)
+        assert normwise(g, r) <= RHS_TOL, name
+
+
+def test_advection_full_run(api, orc):
+    """Smooth periodic advection, N = 200, CFL 0.5 (dt = 0.5 dx), to t = 2."""
+    note("advection full run N=200")
+    u0, dx = I.advection_smooth(200)
+    nsteps = 400
+    ug = to_dev(u0)
+    api.rk3_run_1d(ug, dx, nsteps, cfl=0.5, prm=api.params("advection", bc="periodic"))
+    ur, _, _ = orc.rk3_run_1d(u0, dx, nsteps, dt=0.5 * dx, sys=orc.SYS_ADV, bc=orc.BC_PERIODIC)
+    assert normwise(ug.cpu().numpy(), ur) <= RUN_TOL
+
+
+def test_euler_run_reduced(api, orc):
+    """Shu-Osher-like data at N = 4096 for 150 steps with CFL dt and per-stage LF alpha:
+    states, dt history and alpha history against the oracle."""
+    note("euler run N=4096 x150")
+    u0, dx = I.shu_osher_like(4096)
+    ug = to_dev(u0)
+    dtg, alg = api.rk3_run_1d(ug, dx, 150, cfl=0.5, record=True)
+    ur, dtr, alr = orc.rk3_run_1d(u0, dx, 150, cfl=0.5)
+    np.testing.assert_allclose(dtg.cpu().numpy(), dtr, rtol=1e-12)
+    np.testing.assert_allclose(alg.cpu().numpy(), alr, rtol=1e-12)
+    assert normwise(ug.cpu().numpy(), ur) <= RUN_TOL
+
+
+def test_euler_step_api(api, orc):
+    note("euler rk3_step_1d")
+    u0 = I.random_smooth_1d(777, seed=8)
+    ug = to_dev(u0)
+    dt = api.rk3_step_1d(ug, 0.01, cfl=0.4)
+    ur, dtr, _ = orc.rk3_step_1d(u0, 0.01, cfl=0.4)
+    assert float(dt.cpu()[0]) == pytest.approx(dtr, rel=1e-13)
+    assert normwise(ug.cpu().numpy(), ur) <= RUN_TOL
+
+
+def test_frozen_schedule_run(api, orc):
+    """dt and per-stage alpha supplied (the frozen schedule of the adjoint)."""
+    note("euler run frozen schedule")
+    u0 = I.random_smooth_1d(1500, seed=9)
+    dts = np.full(7, 2e-3)
+    als = np.linspace(2.0, 2.6, 21).reshape(7, 3)
+    ug = to_dev(u0)
+    api.rk3_run_1d(ug, 0.01, 7, dt=to_dev(dts), alpha=to_dev(als), prm=api.params(
+        "euler", bc="periodic"))
+    ur, _, _ = orc.rk3_run_1d(u0, 0.01, 7, dt=dts, alpha=als, bc=orc.BC_PERIODIC)
+    assert normwise(ug.cpu().numpy(), ur) <= RUN_TOL
+
+
+def test_full_size_rhs_and_steps(api, orc):
+    """N = 2^20 (the benchmark size), launch configuration of the benchmark: one RHS and
+    three RK3 steps against the oracle on every cell."""
+    n = 1 << 20
+    note("full size N=2^20 rhs + 3 steps")
+    u0, dx = I.shu_osher_like(n)
+    g = api.rhs_1d(to_dev(u0), dx).cpu().numpy()
+    r, _ = orc.rhs_1d(u0, dx)
+    assert normwise(g, r) <= RHS_TOL
+    ug = to_dev(u0)
+    api.rk3_run_1d(ug, dx, 3, cfl=0.5)
+    ur, _, _ = orc.rk3_run_1d(u0, dx, 3, cfl=0.5)
+    assert normwise(ug.cpu().numpy(), ur) <= RUN_TOL
+
+
+def test_full_size_conservation(api):
+    """N = 2^20 for the full 1000 steps: the edges stay at constant states (the shock moves
+    ~0.004 from x = -4), so sum_i U_i dx changes by exactly t_end (F(U_left) - F(U_right)),
+    up to rounding; positivity of rho and p holds throughout."""
+    import torch
+    n = 1 << 20
+    note("full size N=2^20 x1000 conservation")
+    u0, dx = I.shu_osher_like(n)
+    ug = to_dev(u0)
+    dth, _ = api.rk3_run_1d(ug, dx, 1000, cfl=0.5, record=True)
+    torch.cuda.synchronize()
+    t_end = float(dth.sum().cpu())
+    u = ug.cpu().numpy()
+
+    def flux(U):
+        rho, m, E = U
+        v = m / rho
+        p = 0.4 * (E - 0.5 * rho * v * v)
+        return np.array([m, m * v + p, v * (E + p)])
+
+    dM = (u.sum(axis=1) - u0.sum(axis=1)) * dx
+    expect = t_end * (flux(u0[:, 0]) - flux(u0[:, -1]))
+    np.testing.assert_allclose(dM, expect, rtol=1e-9, atol=1e-9)
+    rho, m, E = u
+    assert rho.min() > 0 and (E - 0.5 * m * m / rho).min() > 0
+    # dt of step 0 from the left state (max |u| + c = 4.5660 ...)
+    assert float(dth[0].cpu()) == pytest.approx(0.5 * dx / 4.56603, rel=1e-4)
+
+
+def test_bad_arguments(api):
+    import torch
+    from paper_2004_07954_amd._lib import WznError
+    u = torch.zeros(3, 5, dtype=torch.float64, device="cuda")
+    with pytest.raises(WznError):
+        api.rhs_1d(u, 0.1)  # n < 6
+    u = torch.ones(3, 10, dtype=torch.float64, device="cuda")
+    with pytest.raises(WznError):
+        api.rhs_1d(u, -1.0)
+    p = api.params()
+    p.q = 2
+    with pytest.raises(WznError):
+        api.rhs_1d(u, 0.1, p)
