@@ -101,7 +101,11 @@ static Recon<T> reconstruct(T a, T b, T c, T d, T e, const OrcParams& P) {
 
   r.IS[0] = T(13) / T(12) * sq(a - T(2) * b + c) + T(1) / T(4) * sq(a - T(4) * b + T(3) * c);
   r.IS[1] = T(13) / T(12) * sq(b - T(2) * c + d) + T(1) / T(4) * sq(b - d);
-  r.IS[2] = T(13) / T(12) * sq(c - T(2) * d + e) + T(1) / T(4) * sq(T(3) * c - T(4) * d + e);
+  // IS2 is written as the mirror image of IS0 (the same expression read from the other end
+  // of the stencil), so that a stencil symmetric about x_i gives IS0 == IS2 exactly in
+  // floating point, as it does in exact arithmetic.  Otherwise tau5 = |IS0 - IS2| is pure
+  // rounding noise there and, with eps = 1e-40, C falls by tens of orders of magnitude.
+  r.IS[2] = T(13) / T(12) * sq(e - T(2) * d + c) + T(1) / T(4) * sq(e - T(4) * d + T(3) * c);
 
   r.tau5 = absv(r.IS[0] - r.IS[2]);
   r.tau8 = sq(a - T(4) * b + T(6) * c - T(4) * d + e);

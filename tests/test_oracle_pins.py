@@ -217,3 +217,16 @@ def test_eno_at_step(orc, f, smooth):
         # stencil (1,1,0,0,0): S_2 = (0,0,0) smooth -> omega_2 dominates, fhat = q_2 = 0
         assert r["omega2"] == pytest.approx(1.0, abs=1e-30)
         assert abs(r["fhat"]) < 1e-38
+
+
+@pytest.mark.parametrize("f", [(1.449137, 2.898275, 2.898275, 2.898275, 1.449137),
+                               (0.3, 1.7, -0.2, 1.7, 0.3), (0.0, 0.0, 1.0, 0.0, 0.0)])
+def test_symmetric_stencil_gives_linear_weights(orc, f):
+    """A stencil symmetric about x_i has IS0 = IS2 exactly, so tau5 = 0 and
+    C = A ((2 IS0 + eps)/eps)^2 >= A (2 IS0/eps)^2 dwarfs tau8/(IS_k + eps) whenever
+    IS0 > 0: the weights are the linear weights c_k to within ~1e-30 (closed form of
+    eq:function and eq:new at tau = 0)."""
+    r = orc.reconstruct(np.array(f))
+    assert r["IS0"] == r["IS2"] and r["tau5"] == 0.0
+    for k, c in enumerate(C_LIN):
+        assert r["omega%d" % k] == pytest.approx(c, rel=1e-14)
