@@ -72,6 +72,40 @@ def cpu_baseline(n, budget_s=12.0):
                       "%.1f s" % (steps, 3 * steps, n, el)}
 
 
+def bench_2d(steps, dtype_name, warmup=3):
+    """Secondary figure: 2D Euler dimension-by-dimension WENO-ZN, 4096^2 four-quadrant data,
+    transmissive, CFL 0.5 (one step = row kernel + column kernel per stage)."""
+    import torch
+    from paper_2004_07954_amd import api, inputs as I
+    nx = ny = 4096
+    tdt = torch.float64 if dtype_name == "f64" else torch.float32
+    u0, dx, dy = I.four_quadrant_random(nx, ny, seed=3)
+    u0t = torch.tensor(u0, dtype=tdt, device="cuda")
+    u = u0t.clone()
+    stage = torch.empty((2, 4, ny, nx), dtype=tdt, device="cuda")
+    prm = api.params("euler", dtype="fp64" if dtype_name == "f64" else "fp32",
+                     eps=1e-40 if dtype_name == "f64" else 1e-30)
+    api.rk3_run_2d(u, dx, dy, warmup, prm=prm, stage=stage)
+    u.copy_(u0t)
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    api.rk3_run_2d(u, dx, dy, steps, prm=prm, stage=stage)
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e)
+    assert torch.isfinite(u).all().item()
+    esz = 8 if dtype_name == "f64" else 4
+    # algorithmic bytes per cell and stage of a fused stage: read U^(s) (+ U^n), write
+    bytes_stage = nx * ny * 4 * esz * (2 + 3 + 3) / 3.0
+    stage_ms = ms / (3 * steps)
+    gbs = bytes_stage / (stage_ms * 1e-3) / 1e9
+    return {"workload": "euler2d_four_quadrant_%dx%d" % (nx, ny), "dtype": dtype_name,
+            "steps": steps, "ms_per_step": ms / steps,
+            "value": nx * ny * 3 * steps / (ms * 1e-3), "unit": "cell-RHS/s",
+            "stage_ms": stage_ms, "hbm_gbs_algorithmic": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +114,8 @@ def main():
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--graph", action="store_true", help="replay the steps as a HIP graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-2d", action="store_true", help="skip the secondary 2D figures")
+    ap.add_argument("--steps-2d", type=int, default=100)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -161,6 +197,10 @@ def main():
                      "kernel_ms": kernel_ms},
         "cpu_baseline": None,
     }
+    if not args.no_2d:
+        log("2D fp64 and fp32, 4096^2")
+        rec["secondary"] = {"euler2d_f64": bench_2d(args.steps_2d, "f64"),
+                            "euler2d_f32": bench_2d(args.steps_2d, "f32")}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         rec["cpu_baseline"] = cpu_baseline(n)

@@ -110,6 +110,34 @@ int32_t wzn_rk3_step_1d(const wzn_params* p, void* u, void* stage, int64_t n, do
                         double cfl, const double* dt_in, double* dt_out, void* ws,
                         void* stream);
 
+/* ---------------------------------------------------------------- 2D (Euler, Sec. 4.4)
+ * Dimension by dimension: L = -(Fhat_{i+1/2,j} - Fhat_{i-1/2,j})/dx - (Ghat_{i,j+1/2} -
+ * Ghat_{i,j-1/2})/dy (eq:2d), each a 1D WENO-ZN reconstruction of the Lax-Friedrichs split
+ * flux with its own global alpha (alpha_x = max(|u| + c), alpha_y = max(|v| + c)).
+ * p->dtype selects fp64 (arrays of double) or fp32 (arrays of float; the weights use a
+ * scale-safe normalisation and eps must be >= 1e-36, e.g. 1e-30).
+ * u, dudt: [4][ny][nx], x fastest; bc_x / bc_y select the boundary in each direction.
+ *
+ * wzn_rhs_2d: dudt = L(u); u and dudt must not alias (dudt is also used as scratch). */
+int32_t wzn_rhs_2d(const wzn_params* p, const void* u, void* dudt, int64_t nx, int64_t ny,
+                   double dx, double dy, void* ws, void* stream);
+
+/* wzn_rk3_run_2d: advance u in place by `nsteps` TVD-RK3 steps.
+ *   stage  device scratch of 2 * 4 * nx * ny elements of the dtype.
+ *   dt_in  NULL: dt = cfl dtx dty / (dtx + dty), dtx = dx / max(|u|+c), dty = dy / max(|v|+c)
+ *          of U^n (Sec. 4.4); else device array [nsteps].
+ *   dt_out NULL or device array [nsteps] receiving every step's dt.
+ * Alphas are reduced per stage unless p->lf_alpha_x / lf_alpha_y are >= 0.
+ * Enqueued as 2 + 6 * nsteps kernels with no host synchronisation. */
+int32_t wzn_rk3_run_2d(const wzn_params* p, void* u, void* stage, int64_t nx, int64_t ny,
+                       double dx, double dy, double cfl, int32_t nsteps, const double* dt_in,
+                       double* dt_out, void* ws, void* stream);
+
+/* wzn_rk3_step_2d: one step; same as wzn_rk3_run_2d with nsteps = 1. */
+int32_t wzn_rk3_step_2d(const wzn_params* p, void* u, void* stage, int64_t nx, int64_t ny,
+                        double dx, double dy, double cfl, const double* dt_in, double* dt_out,
+                        void* ws, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

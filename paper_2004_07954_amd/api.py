@@ -137,3 +137,55 @@ def rk3_step_1d(u, dx, cfl=0.5, prm=None, dt=None, stage=None):
                                 float(cfl), _ptr(dt_t), _ptr(dt_o), _ptr(workspace(u.device)),
                                 _stream()))
     return dt_o
+
+
+def _check_state_2d(u, name="u"):
+    if not isinstance(u, torch.Tensor) or not u.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+    if u.dtype not in (torch.float64, torch.float32):
+        raise TypeError("%s must be float64 or float32" % name)
+    if not u.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if u.dim() != 3 or u.shape[0] != 4:
+        raise ValueError("%s must have shape [4, ny, nx], got %s" % (name, tuple(u.shape)))
+
+
+def _params_2d(prm, u):
+    prm = prm or params("euler", eps=1e-30 if u.dtype == torch.float32 else 1e-40)
+    want = _lib.WZN_FP32 if u.dtype == torch.float32 else _lib.WZN_FP64
+    if prm.dtype != want:
+        raise ValueError("params dtype does not match the tensor dtype")
+    return prm
+
+
+def rhs_2d(u, dx, dy, prm=None, out=None):
+    """L(u) for u[4, ny, nx] (fp64 or fp32, with matching params dtype)."""
+    _check_state_2d(u)
+    prm = _params_2d(prm, u)
+    out = torch.empty_like(u) if out is None else out
+    _check_state_2d(out, "out")
+    check(lib().wzn_rhs_2d(C.byref(prm), _ptr(u), _ptr(out), u.shape[2], u.shape[1], float(dx),
+                           float(dy), _ptr(workspace(u.device)), _stream()))
+    return out
+
+
+def rk3_run_2d(u, dx, dy, nsteps, cfl=0.5, prm=None, dt=None, stage=None, record=False):
+    """Advance u[4, ny, nx] in place by nsteps TVD-RK3 steps; record=True returns the dt
+    history (device tensor [nsteps])."""
+    _check_state_2d(u)
+    prm = _params_2d(prm, u)
+    if stage is None:
+        stage = torch.empty((2,) + tuple(u.shape), dtype=u.dtype, device=u.device)
+    if stage.numel() < 2 * u.numel() or not stage.is_contiguous() or stage.dtype != u.dtype:
+        raise ValueError("stage must be a contiguous tensor of 2 * u.numel() elements")
+    if dt is None:
+        dt_t = None
+    elif isinstance(dt, (int, float)):
+        dt_t = torch.full((nsteps,), float(dt), dtype=torch.float64, device=u.device)
+    else:
+        dt_t = _dev_f64(dt, nsteps, "dt", u.device)
+    dt_o = torch.empty(nsteps, dtype=torch.float64, device=u.device) if record else None
+    check(lib().wzn_rk3_run_2d(C.byref(prm), _ptr(u), _ptr(stage), u.shape[2], u.shape[1],
+                               float(dx), float(dy), float(cfl), int(nsteps), _ptr(dt_t),
+                               _ptr(dt_o), _ptr(workspace(u.device)), _stream()))
+    return dt_o

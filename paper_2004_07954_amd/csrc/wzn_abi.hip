@@ -76,6 +76,23 @@ static int check_1d(const wzn_params* p, int64_t n, double dx, void* ws) {
   return WZN_OK;
 }
 
+static int check_2d(const wzn_params* p, int64_t nx, int64_t ny, double dx, double dy, void* ws) {
+  int st = check_params(p, true);
+  if (st) return st;
+  if (p->system != WZN_EULER) return set_error(WZN_ERR_ARG, "2D supports the Euler system only");
+  if (nx < 6 || ny < 6)
+    return set_error(WZN_ERR_SIZE, "nx = %lld, ny = %lld: both must be >= 6", (long long)nx,
+                     (long long)ny);
+  if (nx > (1 << 24) || ny > (1 << 24) || nx * ny > ((int64_t)1 << 36))
+    return set_error(WZN_ERR_SIZE, "grid %lld x %lld too large", (long long)nx, (long long)ny);
+  if (!(dx > 0.0) || !(dy > 0.0)) return set_error(WZN_ERR_ARG, "dx and dy must be positive");
+  if (p->dtype == WZN_FP32 && !(p->eps >= 1e-36))
+    return set_error(WZN_ERR_ARG, "fp32 needs eps >= 1e-36 (16 eps must be a normal float)");
+  if (!ws) return set_error(WZN_ERR_ARG, "workspace is NULL");
+  if (((uintptr_t)ws) & 255) return set_error(WZN_ERR_ARG, "workspace not 256-byte aligned");
+  return WZN_OK;
+}
+
 }  // namespace wzn
 
 using namespace wzn;
@@ -149,6 +166,44 @@ int32_t wzn_rk3_step_1d(const wzn_params* p, void* u, void* stage, int64_t n, do
                         double cfl, const double* dt_in, double* dt_out, void* ws,
                         void* stream) {
   return wzn_rk3_run_1d(p, u, stage, n, dx, cfl, 1, dt_in, nullptr, dt_out, nullptr, ws, stream);
+}
+
+int32_t wzn_rhs_2d(const wzn_params* p, const void* u, void* dudt, int64_t nx, int64_t ny,
+                   double dx, double dy, void* ws, void* stream) {
+  g_err[0] = 0;
+  int st = check_2d(p, nx, ny, dx, dy, ws);
+  if (st) return st;
+  if (!u || !dudt) return set_error(WZN_ERR_ARG, "u or dudt is NULL");
+  if (u == dudt) return set_error(WZN_ERR_ARG, "u and dudt must not alias");
+  Workspace w = make_workspace(ws);
+  if (p->dtype == WZN_FP32)
+    return rhs_2d_t<float>(p, (const float*)u, (float*)dudt, nx, ny, dx, dy, &w,
+                           (hipStream_t)stream);
+  return rhs_2d_t<double>(p, (const double*)u, (double*)dudt, nx, ny, dx, dy, &w,
+                          (hipStream_t)stream);
+}
+
+int32_t wzn_rk3_run_2d(const wzn_params* p, void* u, void* stage, int64_t nx, int64_t ny,
+                       double dx, double dy, double cfl, int32_t nsteps, const double* dt_in,
+                       double* dt_out, void* ws, void* stream) {
+  g_err[0] = 0;
+  int st = check_2d(p, nx, ny, dx, dy, ws);
+  if (st) return st;
+  if (!u || !stage) return set_error(WZN_ERR_ARG, "u or stage is NULL");
+  if (nsteps < 0) return set_error(WZN_ERR_ARG, "nsteps < 0");
+  if (!dt_in && !(cfl > 0.0)) return set_error(WZN_ERR_ARG, "cfl must be positive");
+  Workspace w = make_workspace(ws);
+  if (p->dtype == WZN_FP32)
+    return rk3_run_2d_t<float>(p, (float*)u, (float*)stage, nx, ny, dx, dy, cfl, nsteps, dt_in,
+                               dt_out, &w, (hipStream_t)stream);
+  return rk3_run_2d_t<double>(p, (double*)u, (double*)stage, nx, ny, dx, dy, cfl, nsteps, dt_in,
+                              dt_out, &w, (hipStream_t)stream);
+}
+
+int32_t wzn_rk3_step_2d(const wzn_params* p, void* u, void* stage, int64_t nx, int64_t ny,
+                        double dx, double dy, double cfl, const double* dt_in, double* dt_out,
+                        void* ws, void* stream) {
+  return wzn_rk3_run_2d(p, u, stage, nx, ny, dx, dy, cfl, 1, dt_in, dt_out, ws, stream);
 }
 
 }  // extern "C"

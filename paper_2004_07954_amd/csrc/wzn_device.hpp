@@ -34,6 +34,9 @@
 
 namespace wzn {
 
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
 // 1/x with one v_rcp_f64 and Newton steps; relative error ~1 ulp for normal x.
 __device__ __forceinline__ double fast_div(double num, double den) {
   double r = __builtin_amdgcn_rcp(den);
@@ -95,6 +98,66 @@ __device__ __forceinline__ void wzn_window(const double* v, double* fh, double e
     const double x2 = (D[m + 1] - D[m + 2]) * (0.3 / 6.0);
     const double nr = __builtin_fma(B0, x0, B2 * x2);
     const double base = __builtin_fma(-1.0 / 6.0, D[m + 1], 0.5 * (v[m + 2] + v[m + 3]));
+    fh[m] = base + fast_div(nr, S);
+  }
+}
+
+
+// ---------------------------------------------------------------------------- fp32 weights
+// In fp32 the product form above underflows (eps^5) and the literal form overflows (C and
+// tau8/eps reach 1e70), so the weights are evaluated in a scale-safe normalisation of the
+// same quantities: dividing every alpha_k by tau8/m with m = min_k s_k,
+//   alpha_k ~ c_k (Q + m/s_k),   Q = C m / tau8 = A (num/den)^2 m / tau8,
+// where m/s_k lies in (0, 1] and Q is clamped at 1e30 (beyond which the weights equal c_k
+// to fp32 precision).  tau8 = 0 gives omega = c exactly.  eps must keep 16 eps normal.
+__device__ __forceinline__ float fast_div(float num, float den) {
+  return num * __builtin_amdgcn_rcpf(den);
+}
+
+template <int K>
+__device__ __forceinline__ void wzn_window(const float* v, float* fh, float eps_s, float A) {
+  constexpr int NG = K + 3;
+  constexpr int ND = K + 2;
+  float g[NG];
+#pragma unroll
+  for (int j = 0; j < NG; ++j) g[j] = v[j + 1] - v[j];
+  float D[ND];
+#pragma unroll
+  for (int j = 0; j < ND; ++j) D[j] = g[j + 1] - g[j];
+  float DD[ND];
+#pragma unroll
+  for (int j = 0; j < ND; ++j) DD[j] = (D[j] * (13.0f / 3.0f)) * D[j];
+#pragma unroll
+  for (int m = 0; m < K; ++m) {
+    const float E0 = __builtin_fmaf(3.0f, g[m + 1], -g[m]);
+    const float E1 = g[m + 1] + g[m + 2];
+    const float E2 = __builtin_fmaf(-3.0f, g[m + 2], g[m + 3]);
+    const float IS0 = __builtin_fmaf(E0, E0, DD[m]);
+    const float IS1 = __builtin_fmaf(E1, E1, DD[m + 1]);
+    const float IS2 = __builtin_fmaf(E2, E2, DD[m + 2]);
+    const float t5 = __builtin_fabsf(IS0 - IS2);
+    const float num = ((IS0 + IS2) - t5) + eps_s;
+    const float den = t5 + eps_s;
+    const float s0 = IS0 + eps_s, s1 = IS1 + eps_s, s2 = IS2 + eps_s;
+    const float b = __builtin_fmaf(-2.0f, D[m + 1], D[m] + D[m + 2]);
+    const float tau = 4.0f * b * b;  // 4 tau8 in the scaled units
+    const float mn = fminf(s0, fminf(s1, s2));
+    const float r = fast_div(num, den);
+    float Q;
+    if (tau > 0.0f) {
+      const float mt = fast_div(mn, tau);
+      Q = fminf(fminf(A * r, 1e30f) * fminf(r * mt, 1e30f), 1e30f);
+    } else {
+      Q = 1e30f;
+    }
+    const float B0 = 0.1f * (Q + fast_div(mn, s0));
+    const float B1 = 0.6f * (Q + fast_div(mn, s1));
+    const float B2 = 0.3f * (Q + fast_div(mn, s2));
+    const float S = B0 + B1 + B2;
+    const float x0 = (D[m] - D[m + 1]) * (1.0f / 3.0f);
+    const float x2 = (D[m + 1] - D[m + 2]) * (1.0f / 6.0f);
+    const float nr = __builtin_fmaf(B0, x0, B2 * x2);
+    const float base = __builtin_fmaf(-1.0f / 6.0f, D[m + 1], 0.5f * (v[m + 2] + v[m + 3]));
     fh[m] = base + fast_div(nr, S);
   }
 }

@@ -41,6 +41,18 @@ int check_launch(const char* what);
 int launch_zero_words(unsigned long long* p, int count, hipStream_t s);
 int launch_fill_double(double* p, double v, hipStream_t s);
 
+template <typename T>
+int launch_speed_max(const T* u, int64_t n, int nv, double gamma, unsigned long long* slot,
+                     unsigned long long* slot_y, hipStream_t s);
+
+template <typename T>
+int rhs_2d_t(const wzn_params* p, const T* u, T* dudt, int64_t nx, int64_t ny, double dx,
+             double dy, Workspace* ws, hipStream_t s);
+template <typename T>
+int rk3_run_2d_t(const wzn_params* p, T* u, T* stage, int64_t nx, int64_t ny, double dx,
+                 double dy, double cfl, int32_t nsteps, const double* dt_in, double* dt_out,
+                 Workspace* ws, hipStream_t s);
+
 int rhs_1d(const wzn_params* p, const double* u, double* dudt, int64_t n, double dx,
            Workspace* ws, hipStream_t s);
 int rk3_run_1d(const wzn_params* p, double* u, double* stage, int64_t n, double dx, double cfl,

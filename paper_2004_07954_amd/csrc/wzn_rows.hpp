@@ -1,0 +1,48 @@
+// Arguments of the row kernel (1D right-hand side / RK stage, 2D x sweep).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "wzn_host.hpp"
+
+namespace wzn {
+
+enum { SYS_ADV = 0, SYS_EULER1 = 1, SYS_EULER2X = 2 };
+enum { MODE_RHS = 0, MODE_STAGE = 1 };
+
+template <typename T>
+struct RowArgs {
+  const T* uin;        // stage input U^(s): component c, row j, cell i at c*plane + j*row_stride + i
+  const T* un;         // U^n for the stage combination, or null when a_s == 0
+  T* out;              // L (MODE_RHS) or U^(s+1) (MODE_STAGE), same layout
+  int64_t n;           // cells per row
+  int64_t plane;       // elements per component
+  int64_t row_stride;  // elements between rows
+  double dx;
+  int bc;
+  int mode;
+  double rk_a, rk_b;
+  double adv, gamma, eps_s, A;
+  // LF alpha of this RHS evaluation: slot (reduced) / array (frozen) / constant
+  const unsigned long long* alpha_slot;
+  const double* alpha_arr;
+  double alpha_const;
+  // dt: array / cfl dx / (speed in a slot) / the dt slot
+  const double* dt_arr;
+  const unsigned long long* dt_speed_slot;
+  const double* dt_slot_read;
+  double cfl;
+  double* dt_slot_write;
+  double* dt_rec;
+  double* alpha_rec;
+  // epilogue (1D only)
+  unsigned long long* speed_next;  // atomic max of |u| + c of the output, or null
+  unsigned long long* slot_zero;   // zeroed by workgroup (0,0), or null
+};
+
+int launch_rows(const RowArgs<double>& a, int sys, int64_t rows, const Tuning1D& tn,
+                hipStream_t s);
+int launch_rows(const RowArgs<float>& a, int sys, int64_t rows, const Tuning1D& tn,
+                hipStream_t s);
+
+}  // namespace wzn
