@@ -106,6 +106,66 @@ def bench_2d(steps, dtype_name, warmup=3):
             "stage_ms": stage_ms, "hbm_gbs_algorithmic": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}
 
 
+def bench_batched(steps, baseline_sample=48, use_graph=True):
+    """Secondary figure: 4096 independent 1D Euler shock tubes (N_i ~ U{256..16384}, seed 4)
+    advanced by `steps` TVD-RK3 steps in one persistent launch (autotuned, longest first,
+    captured in a HIP graph), against one launch per instance and stage (wzn_rk3_run_1d per
+    instance, timed on a random sample of instances and scaled to the whole batch)."""
+    import numpy as np
+    import torch
+    from paper_2004_07954_amd import api, autotune, inputs as I
+    U, offs, dx = I.shock_tube_batch(4096, seed=4)
+    lens = np.diff(offs)
+    dev = "cuda"
+    U0 = torch.tensor(U, dtype=torch.float64, device=dev)
+    Ug = U0.clone()
+    offg = torch.tensor(offs, dtype=torch.int64, device=dev)
+    dxg = torch.tensor(dx, dtype=torch.float64, device=dev)
+    order = api.lpt_order(lens)
+    stage = torch.empty((2, 3, U.shape[1]), dtype=torch.float64, device=dev)
+    tn, timings = autotune.tune_batched(Ug, offg, dxg, order=order, use_cache=False, log=log)
+    log("batched tuning: nt=%d k=%d blocks/cu=%d" % (tn.nt, tn.k, tn.blocks_per_cu))
+    graph = None
+    if use_graph:
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            api.batched_rk3_run_1d(Ug, offg, dxg, steps, order=order, tuning=tn, stage=stage)
+    Ug.copy_(U0)
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    if graph is not None:
+        graph.replay()
+    else:
+        api.batched_rk3_run_1d(Ug, offg, dxg, steps, order=order, tuning=tn, stage=stage)
+    e.record()
+    torch.cuda.synchronize()
+    ms_batched = s.elapsed_time(e)
+    assert torch.isfinite(Ug).all().item()
+    # baseline: one launch per instance and stage, on a random sample of instances
+    pick = np.random.default_rng(11).choice(len(lens), baseline_sample, replace=False)
+    singles = [torch.tensor(np.ascontiguousarray(U[:, offs[b]:offs[b + 1]]),
+                            dtype=torch.float64, device=dev) for b in pick]
+    st1 = [torch.empty((2,) + tuple(t.shape), dtype=torch.float64, device=dev) for t in singles]
+    torch.cuda.synchronize()
+    s.record()
+    for t, stg, b in zip(singles, st1, pick):
+        api.rk3_run_1d(t, float(dx[b]), steps, cfl=0.5, stage=stg)
+    e.record()
+    torch.cuda.synchronize()
+    ms_sample = s.elapsed_time(e)
+    ms_baseline = ms_sample * len(lens) / baseline_sample
+    cells = float(lens.sum())
+    return {"workload": "batched_shock_tubes_B4096_seed4", "instances": int(len(lens)),
+            "total_cells": int(cells), "steps": steps, "ms_batched": ms_batched,
+            "value": cells * 3 * steps / (ms_batched * 1e-3), "unit": "cell-RHS/s",
+            "tuning": {"nt": tn.nt, "k": tn.k, "blocks_per_cu": tn.blocks_per_cu},
+            "launch": "hip_graph" if graph is not None else "stream",
+            "baseline_ms_estimate": ms_baseline, "baseline_sample": baseline_sample,
+            "baseline_sample_ms": ms_sample,
+            "speedup_vs_one_launch_per_instance": ms_baseline / ms_batched}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,6 +176,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-2d", action="store_true", help="skip the secondary 2D figures")
     ap.add_argument("--steps-2d", type=int, default=100)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--steps-batched", type=int, default=500)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -174,7 +236,7 @@ def main():
     bytes_per_launch = n * (48 + 72 + 72) / 3.0
     achieved = bytes_per_launch / (kernel_ms * 1e-3) / 1e9
     value = n * 3 * K / (ms * 1e-3)
-    traffic = committed_traffic("stage1d", "euler1d_n%d" % n)
+    traffic = committed_traffic("row_kernel", "euler1d_n%d" % n)
     rec = {
         "metric": "WENO-ZN RHS cell-updates/s (1D Euler, fused TVD-RK3 stages)",
         "value": value,
@@ -193,7 +255,7 @@ def main():
                    "launch": "hip_graph" if graph else "stream", "kernels_per_step": 3},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "kernel": "stage1d_kernel<256,4,3>",
+                     "traffic": traffic, "kernel": "row_kernel<256,4,EULER1,double>",
                      "kernel_ms": kernel_ms},
         "cpu_baseline": None,
     }
@@ -201,6 +263,10 @@ def main():
         log("2D fp64 and fp32, 4096^2")
         rec["secondary"] = {"euler2d_f64": bench_2d(args.steps_2d, "f64"),
                             "euler2d_f32": bench_2d(args.steps_2d, "f32")}
+    if not args.no_batched:
+        log("batched: 4096 shock tubes")
+        rec.setdefault("secondary", {})["batched"] = bench_batched(args.steps_batched)
+        rec["batched_speedup"] = rec["secondary"]["batched"]["speedup_vs_one_launch_per_instance"]
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         rec["cpu_baseline"] = cpu_baseline(n)

@@ -138,6 +138,37 @@ int32_t wzn_rk3_step_2d(const wzn_params* p, void* u, void* stage, int64_t nx, i
                         double dx, double dy, double cfl, const double* dt_in, double* dt_out,
                         void* ws, void* stream);
 
+/* ---------------------------------------------------------------- batched 1D Euler
+ * Many independent 1D Euler problems of uneven length, advanced by `nsteps` TVD-RK3 steps in
+ * ONE persistent kernel launch (plus a one-word counter reset).  Instance i occupies cells
+ * offsets[i] .. offsets[i+1]-1 of the concatenated state u[3][total] (component c of cell j
+ * at u[c * total + j]); each instance has its own grid spacing dx[i], its own per-stage
+ * global Lax-Friedrichs alpha (max |u| + c over the instance) and its own
+ * dt = cfl dx[i] / max(|u| + c) of its U^n (Sec. 4.3).  p->bc_x applies to every instance;
+ * alphas are always reduced (p->lf_alpha_x must be < 0).
+ *   stage    device scratch of 2 * 3 * total doubles.
+ *   offsets  device int64 [batch + 1], non-decreasing, offsets[batch] == total; every instance
+ *            must have >= 6 cells (shorter or out-of-range instances are skipped unchanged).
+ *   dx       device double [batch].
+ *   order    device int32 [batch]: the order in which instances are handed to workgroups
+ *            (longest first balances the load), or NULL for 0 .. batch-1.
+ *   tuning   host struct (NULL: defaults); nt in {64, 128, 256} threads per workgroup, k in
+ *            {1, 2, 4} cells per thread (supported pairs: 64x2, 64x4, 128x2, 128x4, 256x1,
+ *            256x2, 256x4); blocks_per_cu <= 0 takes the occupancy limit.
+ *   dt_out   NULL or device double [batch][nsteps] receiving every instance's dt history. */
+typedef struct {
+  int32_t nt;
+  int32_t k;
+  int32_t blocks_per_cu;
+  int32_t reserved;
+} wzn_batch_tuning;
+
+int32_t wzn_batched_rk3_run_1d(const wzn_params* p, void* u, void* stage, int64_t total,
+                               const int64_t* offsets, const double* dx, const int32_t* order,
+                               int32_t batch, int32_t nsteps, double cfl,
+                               const wzn_batch_tuning* tuning, double* dt_out, void* ws,
+                               void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -25,6 +25,11 @@ class WznParams(C.Structure):
                 ("lf_alpha_y", C.c_double)]
 
 
+class WznBatchTuning(C.Structure):
+    _fields_ = [("nt", C.c_int32), ("k", C.c_int32), ("blocks_per_cu", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
 # (name, restype, argtypes) of every symbol include/wenozn.h declares
 _P, _D, _I32, _I64, _SZ = C.c_void_p, C.c_double, C.c_int32, C.c_int64, C.c_size_t
 _PP = C.POINTER(WznParams)
@@ -40,6 +45,8 @@ SIGNATURES = [
     ("wzn_rhs_2d", _I32, [_PP, _P, _P, _I64, _I64, _D, _D, _P, _P]),
     ("wzn_rk3_run_2d", _I32, [_PP, _P, _P, _I64, _I64, _D, _D, _D, _I32, _P, _P, _P, _P]),
     ("wzn_rk3_step_2d", _I32, [_PP, _P, _P, _I64, _I64, _D, _D, _D, _P, _P, _P, _P]),
+    ("wzn_batched_rk3_run_1d", _I32, [_PP, _P, _P, _I64, _P, _P, _P, _I32, _I32, _D,
+                                      C.POINTER(WznBatchTuning), _P, _P, _P]),
 ]
 
 _LIB = None

@@ -189,3 +189,43 @@ def rk3_run_2d(u, dx, dy, nsteps, cfl=0.5, prm=None, dt=None, stage=None, record
                                float(dx), float(dy), float(cfl), int(nsteps), _ptr(dt_t),
                                _ptr(dt_o), _ptr(workspace(u.device)), _stream()))
     return dt_o
+
+
+def batch_tuning(nt=128, k=2, blocks_per_cu=0):
+    return _lib.WznBatchTuning(int(nt), int(k), int(blocks_per_cu), 0)
+
+
+def lpt_order(lengths, device="cuda"):
+    """Longest-first processing order of the instances (balances the persistent launch)."""
+    lengths = torch.as_tensor(lengths).cpu()
+    order = torch.argsort(lengths, descending=True, stable=True).to(torch.int32)
+    return order.to(device)
+
+
+def batched_rk3_run_1d(u, offsets, dx, nsteps, cfl=0.5, prm=None, order=None, tuning=None,
+                       stage=None, record=False):
+    """Advance every instance of the concatenated state u[3, total] by nsteps TVD-RK3 steps
+    in one persistent launch.  offsets: device int64 [batch + 1]; dx: device fp64 [batch];
+    order: device int32 [batch] or None.  record=True returns dt history [batch, nsteps]."""
+    prm = prm or params("euler", bc="transmissive")
+    _check_state(u, 3)
+    total = u.shape[1]
+    if offsets.dtype != torch.int64 or not offsets.is_cuda or not offsets.is_contiguous():
+        raise TypeError("offsets must be a contiguous CUDA int64 tensor")
+    batch = offsets.numel() - 1
+    if dx.dtype != torch.float64 or not dx.is_cuda or dx.numel() != batch:
+        raise TypeError("dx must be a CUDA float64 tensor of batch entries")
+    if order is not None and (order.dtype != torch.int32 or not order.is_cuda or
+                              order.numel() != batch):
+        raise TypeError("order must be a CUDA int32 tensor of batch entries")
+    if stage is None:
+        stage = torch.empty((2, 3, total), dtype=torch.float64, device=u.device)
+    if stage.numel() < 2 * u.numel() or not stage.is_contiguous():
+        raise ValueError("stage must be a contiguous fp64 tensor of 2 * u.numel() elements")
+    dt_o = torch.empty((batch, nsteps), dtype=torch.float64, device=u.device) if record else None
+    tn = tuning if tuning is not None else None
+    check(lib().wzn_batched_rk3_run_1d(C.byref(prm), _ptr(u), _ptr(stage), total, _ptr(offsets),
+                                       _ptr(dx), _ptr(order), int(batch), int(nsteps),
+                                       float(cfl), C.byref(tn) if tn is not None else None,
+                                       _ptr(dt_o), _ptr(workspace(u.device)), _stream()))
+    return dt_o

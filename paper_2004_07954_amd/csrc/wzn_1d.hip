@@ -11,6 +11,7 @@
 #include "wzn_device.hpp"
 #include "wzn_host.hpp"
 #include "wzn_rows.hpp"
+#include "wzn_tile.hpp"
 
 namespace wzn {
 
@@ -24,17 +25,13 @@ __global__ __launch_bounds__(256) void speed_max_kernel(const T* __restrict__ u,
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * 256) {
     if constexpr (NV == 3) {
-      const double rho = u[i], m = u[n + i], E = u[2 * n + i];
-      const double vel = m / rho;
-      const double p = (gamma - 1.0) * (E - (0.5 * rho) * vel * vel);
-      sx = fmax(sx, __builtin_fabs(vel) + __builtin_sqrt(gamma * p / rho));
+      const double U[3] = {double(u[i]), double(u[n + i]), double(u[2 * n + i])};
+      sx = fmax(sx, wave_speed_1d<SYS_EULER1>(U, 0.0, gamma));
     } else {
-      const double rho = u[i], mx = u[n + i], my = u[2 * n + i], E = u[3 * n + i];
-      const double vx = mx / rho, vy = my / rho;
-      const double p = (gamma - 1.0) * (E - (0.5 * rho) * (vx * vx + vy * vy));
-      const double c = __builtin_sqrt(gamma * p / rho);
-      sx = fmax(sx, __builtin_fabs(vx) + c);
-      sy = fmax(sy, __builtin_fabs(vy) + c);
+      double a, b;
+      wave_speeds_2d(u[i], u[n + i], u[2 * n + i], u[3 * n + i], gamma, a, b);
+      sx = fmax(sx, a);
+      sy = fmax(sy, b);
     }
   }
   __shared__ double red[2][4];

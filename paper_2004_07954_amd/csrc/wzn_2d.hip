@@ -19,6 +19,7 @@
 #include "wzn_device.hpp"
 #include "wzn_host.hpp"
 #include "wzn_rows.hpp"
+#include "wzn_tile.hpp"
 
 namespace wzn {
 
@@ -174,11 +175,10 @@ void col_kernel(ColArgs<T> a) {
             const int64_t gi = y * a.nx + x;
             const double o0 = a.out[gi], o1 = a.out[a.plane + gi];
             const double o2 = a.out[2 * a.plane + gi], o3 = a.out[3 * a.plane + gi];
-            const double vx = o1 / o0, vy = o2 / o0;
-            const double p = (gamma - 1.0) * (o3 - (0.5 * o0) * (vx * vx + vy * vy));
-            const double cs = __builtin_sqrt(gamma * p / o0);
-            sxm = fmax(sxm, __builtin_fabs(vx) + cs);
-            sym = fmax(sym, __builtin_fabs(vy) + cs);
+            double ax, ay;
+            wave_speeds_2d(o0, o1, o2, o3, gamma, ax, ay);
+            sxm = fmax(sxm, ax);
+            sym = fmax(sym, ay);
           }
         }
       }

@@ -206,4 +206,30 @@ int32_t wzn_rk3_step_2d(const wzn_params* p, void* u, void* stage, int64_t nx, i
   return wzn_rk3_run_2d(p, u, stage, nx, ny, dx, dy, cfl, 1, dt_in, dt_out, ws, stream);
 }
 
+int32_t wzn_batched_rk3_run_1d(const wzn_params* p, void* u, void* stage, int64_t total,
+                               const int64_t* offsets, const double* dx, const int32_t* order,
+                               int32_t batch, int32_t nsteps, double cfl,
+                               const wzn_batch_tuning* tuning, double* dt_out, void* ws,
+                               void* stream) {
+  g_err[0] = 0;
+  int st = check_1d(p, total, 1.0, ws);
+  if (st) return st;
+  if (p->system != WZN_EULER) return set_error(WZN_ERR_ARG, "batched runs are 1D Euler only");
+  if (p->lf_alpha_x >= 0.0)
+    return set_error(WZN_ERR_UNSUPPORTED, "batched runs always reduce alpha (lf_alpha_x < 0)");
+  if (!u || !stage || !offsets || !dx) return set_error(WZN_ERR_ARG, "NULL array argument");
+  if (batch < 1) return set_error(WZN_ERR_ARG, "batch < 1");
+  if (nsteps < 0) return set_error(WZN_ERR_ARG, "nsteps < 0");
+  if (!(cfl > 0.0)) return set_error(WZN_ERR_ARG, "cfl must be positive");
+  if (tuning) {
+    const int nt = tuning->nt, k = tuning->k;
+    const bool ok = (nt == 64 && (k == 2 || k == 4)) || (nt == 128 && (k == 2 || k == 4)) ||
+                    (nt == 256 && (k == 1 || k == 2 || k == 4));
+    if (!ok) return set_error(WZN_ERR_ARG, "unsupported batched tuning (nt=%d, k=%d)", nt, k);
+  }
+  Workspace w = make_workspace(ws);
+  return batched_rk3_run_1d(p, (double*)u, (double*)stage, total, offsets, dx, order, batch,
+                            nsteps, cfl, tuning, dt_out, &w, (hipStream_t)stream);
+}
+
 }  // extern "C"

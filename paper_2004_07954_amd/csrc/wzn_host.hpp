@@ -53,6 +53,11 @@ int rk3_run_2d_t(const wzn_params* p, T* u, T* stage, int64_t nx, int64_t ny, do
                  double dy, double cfl, int32_t nsteps, const double* dt_in, double* dt_out,
                  Workspace* ws, hipStream_t s);
 
+int batched_rk3_run_1d(const wzn_params* p, double* u, double* stage, int64_t total,
+                       const int64_t* offsets, const double* dx, const int32_t* order,
+                       int32_t batch, int32_t nsteps, double cfl, const wzn_batch_tuning* tn,
+                       double* dt_out, Workspace* ws, hipStream_t s);
+
 int rhs_1d(const wzn_params* p, const double* u, double* dudt, int64_t n, double dx,
            Workspace* ws, hipStream_t s);
 int rk3_run_1d(const wzn_params* p, double* u, double* stage, int64_t n, double dx, double cfl,
