@@ -92,11 +92,19 @@ def test_batched_order_and_blocks_invariance(api):
     np.testing.assert_array_equal(a.cpu().numpy(), b.cpu().numpy())
 
 
+# Instance 1767 of the seed-4 batch (N = 12399; left rho 4.09, u 0.61, p 0.13; right rho 0.23,
+# u -0.52, p 1.99) loses positivity after ~200 steps: the CPU oracle run of that instance
+# alone reaches rho < 0 at step ~220 and NaN by step ~275.  Component-wise Lax-Friedrichs
+# WENO-ZN carries no positivity limiter; the instances are independent, so the NaNs stay in
+# that instance.
+UNSTABLE = {1767}
+
+
 def test_batched_full_workload_sampled(api):
     """The benchmark workload (4096 instances, N_i in [256, 16384], seed 4) for 500 steps in
-    the launch configuration the benchmark times (autotuned): a sample of 12 instances is
-    re-run one by one through the single-instance path and must match bit for bit; every
-    instance stays positive."""
+    the launch configuration the benchmark times (autotuned): a sample of instances is re-run
+    one by one through the single-instance path and must match bit for bit (including the
+    unstable instance's NaNs); every other instance stays finite with rho, p > 0."""
     import torch
     from paper_2004_07954_amd import autotune
     note("batched full workload 4096 x 500")
@@ -109,8 +117,14 @@ def test_batched_full_workload_sampled(api):
     api.batched_rk3_run_1d(Ug, offg, dxg, 500, order=order, tuning=tn)
     torch.cuda.synchronize()
     Ub = Ug.cpu().numpy()
-    assert np.isfinite(Ub).all() and Ub[0].min() > 0
-    for b in np.random.default_rng(7).choice(4096, 12, replace=False):
+    rho, m, E = Ub
+    with np.errstate(invalid="ignore", divide="ignore"):
+        p = 0.4 * (E - 0.5 * m * m / rho)
+    bad = ~np.isfinite(Ub).all(axis=0) | (rho <= 0) | (p <= 0)
+    bad_inst = set(np.unique(np.searchsorted(offs, np.nonzero(bad)[0], side="right") - 1).tolist())
+    assert bad_inst == UNSTABLE, bad_inst
+    sample = list(np.random.default_rng(7).choice(4096, 12, replace=False)) + sorted(UNSTABLE)
+    for b in sample:
         sl = slice(offs[b], offs[b + 1])
         u1 = torch.tensor(np.ascontiguousarray(U[:, sl]), dtype=torch.float64, device="cuda")
         api.rk3_run_1d(u1, dx[b], 500, cfl=0.5)
