@@ -170,6 +170,39 @@ def bench_batched(steps, baseline_sample=48, use_graph=True):
             "nonfinite_instances": bad_inst}
 
 
+def bench_adjoint(n=65536, nsteps=400, ckpt=20, reps=3):
+    """Secondary figure: the discrete adjoint of a periodic 1D Euler run (N = 65536, 400 steps,
+    checkpoints every 20; loss 1/2 ||rho_T - rho_target||^2).  Reports the forward time (run
+    with checkpoints and the recorded schedule) and the backward time (segment recomputation
+    plus the adjoint kernels), medians of `reps` repetitions."""
+    import numpy as np
+    import torch
+    from paper_2004_07954_amd import adjoint, api, inputs as I
+    u0, ut, dx = I.adjoint_case(n=n, seed=5)
+    U0 = torch.tensor(u0, dtype=torch.float64, device="cuda")
+    rho_t = torch.tensor(ut[0], dtype=torch.float64, device="cuda")
+    prm = api.params("euler", bc="periodic")
+    fw, bw = [], []
+    for _ in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        UT, dts, als, ckpts = adjoint.forward_checkpointed(U0, dx, nsteps, 0.5, prm, ckpt)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        lamT = torch.zeros_like(UT)
+        lamT[0] = UT[0] - rho_t
+        lam0 = adjoint.backward_checkpointed(lamT, dx, dts, als, ckpts, ckpt, prm)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        fw.append(t1 - t0)
+        bw.append(t2 - t1)
+    fw, bw = float(np.median(fw[1:])), float(np.median(bw[1:]))
+    assert torch.isfinite(lam0).all().item()
+    return {"workload": "adjoint_euler1d_periodic_n%d_%dsteps_ckpt%d" % (n, nsteps, ckpt),
+            "forward_ms": fw * 1e3, "backward_ms": bw * 1e3, "adjoint_fwd_ratio": bw / fw,
+            "timing": "host wall clock around synchronised GPU work, median of %d" % reps}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -182,6 +215,7 @@ def main():
     ap.add_argument("--steps-2d", type=int, default=100)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--steps-batched", type=int, default=500)
+    ap.add_argument("--no-adjoint", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -271,6 +305,10 @@ def main():
         log("batched: 4096 shock tubes")
         rec.setdefault("secondary", {})["batched"] = bench_batched(args.steps_batched)
         rec["batched_speedup"] = rec["secondary"]["batched"]["speedup_vs_one_launch_per_instance"]
+    if not args.no_adjoint:
+        log("adjoint: N=65536, 400 steps")
+        rec.setdefault("secondary", {})["adjoint"] = bench_adjoint()
+        rec["adjoint_fwd_ratio"] = rec["secondary"]["adjoint"]["adjoint_fwd_ratio"]
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         rec["cpu_baseline"] = cpu_baseline(n)

@@ -169,6 +169,29 @@ int32_t wzn_batched_rk3_run_1d(const wzn_params* p, void* u, void* stage, int64_
                                const wzn_batch_tuning* tuning, double* dt_out, void* ws,
                                void* stream);
 
+/* ---------------------------------------------------------------- discrete adjoint (1D Euler)
+ * Vector-Jacobian products of the maps the forward entry points evaluate, with the
+ * Lax-Friedrichs alpha of every stage and the dt of every step frozen (constants recorded by
+ * the forward run).  fp64 only.
+ *
+ * wzn_rhs_1d_vjp: out = J(u)^T mu, J = dL/dU at u (eq:2 with the WENO-ZN fluxes of Sec. 3).
+ *   alpha = p->lf_alpha_x if >= 0, else max(|u| + c) of u, held constant.  All arrays
+ *   [3][n]; out must not alias u or mu. */
+int32_t wzn_rhs_1d_vjp(const wzn_params* p, const void* u, const void* mu, void* out, int64_t n,
+                       double dx, void* ws, void* stream);
+
+/* wzn_rk3_step_1d_vjp: lam_prev = (dU^{n+1}/dU^n)^T lam_next for one TVD-RK3 step.
+ *   stages   [3][3][n]: U^n, U1, U2 of the step (as the forward computed them).
+ *   scratch  device scratch of 3 * 3 * n doubles.
+ *   dt       device pointer to the step's dt; alpha3: device pointer to its 3 stage alphas.
+ * Three fused kernels:
+ *   lam2 = 2/3 (lam3 + dt J(U2)^T lam3), lam1 = 1/4 (lam2 + dt J(U1)^T lam2),
+ *   lam_prev = 1/3 lam3 + 3/4 lam2 + lam1 + dt J(U^n)^T lam1.
+ * lam_prev must not alias lam_next, stages or scratch. */
+int32_t wzn_rk3_step_1d_vjp(const wzn_params* p, const void* stages, const void* lam_next,
+                            void* lam_prev, void* scratch, int64_t n, double dx,
+                            const double* dt, const double* alpha3, void* ws, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -47,8 +47,13 @@ typedef std::complex<double> cplx;
 // ---------------------------------------------------------------- scalar helpers
 static inline double absv(double x) { return std::fabs(x); }
 static inline f128 absv(f128 x) { return fabsq(x); }
-// |z| for the complex step: the analytic continuation of |x| away from x = 0.
-static inline cplx absv(cplx z) { return z.real() < 0.0 ? -z : z; }
+// |z| for the complex step: the analytic continuation of |x| away from x = 0; at x = 0 the
+// derivative is taken as 0 (the kink of tau5 = |IS0 - IS2| at symmetric stencils).
+static inline cplx absv(cplx z) {
+  if (z.real() > 0.0) return z;
+  if (z.real() < 0.0) return -z;
+  return cplx(0.0, 0.0);
+}
 
 static inline double realv(double x) { return x; }
 static inline double realv(f128 x) { return (double)x; }

@@ -47,6 +47,8 @@ SIGNATURES = [
     ("wzn_rk3_step_2d", _I32, [_PP, _P, _P, _I64, _I64, _D, _D, _D, _P, _P, _P, _P]),
     ("wzn_batched_rk3_run_1d", _I32, [_PP, _P, _P, _I64, _P, _P, _P, _I32, _I32, _D,
                                       C.POINTER(WznBatchTuning), _P, _P, _P]),
+    ("wzn_rhs_1d_vjp", _I32, [_PP, _P, _P, _P, _I64, _D, _P, _P]),
+    ("wzn_rk3_step_1d_vjp", _I32, [_PP, _P, _P, _P, _P, _I64, _D, _P, _P, _P, _P]),
 ]
 
 _LIB = None

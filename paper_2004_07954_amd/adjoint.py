@@ -1,0 +1,90 @@
+"""Discrete adjoint of a 1D Euler WENO-ZN TVD-RK3 run with checkpointed recomputation.
+
+The forward pass runs the fused stage kernels, records the dt of every step and the
+Lax-Friedrichs alpha of every stage, and keeps the state every `ckpt_every` steps.  The
+backward pass walks the segments in reverse: it recomputes the stage states of a segment from
+its checkpoint with the recorded (frozen) schedule, then applies the hand-written
+vector-Jacobian kernels of the TVD-RK3 step in reverse order.  The gradient is that of the
+forward map with dt and alphas held at their recorded values.
+"""
+import torch
+
+from . import api
+
+
+def forward_checkpointed(U0, dx, nsteps, cfl=0.5, prm=None, ckpt_every=20):
+    """Returns (U_T, dt[nsteps], alpha[nsteps, 3], checkpoints).  checkpoints[k] is the state
+    after k * ckpt_every steps (k = 0 .. number of segments - 1)."""
+    prm = prm or api.params("euler", bc="periodic")
+    U = U0.clone()
+    stage = torch.empty((2,) + tuple(U.shape), dtype=U.dtype, device=U.device)
+    dts = torch.empty(nsteps, dtype=torch.float64, device=U.device)
+    als = torch.empty((nsteps, 3), dtype=torch.float64, device=U.device)
+    ckpts = []
+    t = 0
+    while t < nsteps:
+        steps = min(ckpt_every, nsteps - t)
+        ckpts.append(U.clone())
+        d, a = api.rk3_run_1d(U, dx, steps, cfl=cfl, prm=prm, stage=stage, record=True)
+        dts[t:t + steps].copy_(d)
+        als[t:t + steps].copy_(a)
+        t += steps
+    return U, dts, als, ckpts
+
+
+def run_frozen(U0, dx, dts, als, prm=None):
+    """Forward run with a recorded schedule (for finite-difference checks)."""
+    prm = prm or api.params("euler", bc="periodic")
+    U = U0.clone()
+    api.rk3_run_1d(U, dx, dts.numel(), dt=dts, alpha=als, prm=prm)
+    return U
+
+
+def backward_checkpointed(lamT, dx, dts, als, ckpts, ckpt_every=20, prm=None):
+    """lam_0 = (dU_T/dU_0)^T lam_T with the frozen schedule."""
+    prm = prm or api.params("euler", bc="periodic")
+    nsteps = dts.numel()
+    n = lamT.shape[1]
+    dev = lamT.device
+    lam = lamT.clone()
+    lam_prev = torch.empty_like(lam)
+    scratch = torch.empty((3, 3, n), dtype=torch.float64, device=dev)
+    seg_stages = torch.empty((ckpt_every, 3, 3, n), dtype=torch.float64, device=dev)
+    nseg = len(ckpts)
+    for sgi in reversed(range(nseg)):
+        t0 = sgi * ckpt_every
+        steps = min(ckpt_every, nsteps - t0)
+        U = ckpts[sgi].clone()
+        for k in range(steps):
+            t = t0 + k
+            seg_stages[k, 0].copy_(U)
+            api.rk3_run_1d(U, dx, 1, dt=dts[t:t + 1], alpha=als[t:t + 1], prm=prm,
+                           stage=seg_stages[k, 1:3])
+        for k in reversed(range(steps)):
+            t = t0 + k
+            api.rk3_step_1d_vjp(seg_stages[k], lam, dts[t:t + 1], als[t], dx, prm=prm,
+                                out=lam_prev, scratch=scratch)
+            lam, lam_prev = lam_prev, lam
+    return lam
+
+
+class WenoZNRK3(torch.autograd.Function):
+    """U_T = RK3^nsteps(U_0) with WENO-ZN right-hand sides; backward = discrete adjoint with
+    checkpointed recomputation (dt and alphas frozen at the forward's values)."""
+
+    @staticmethod
+    def forward(ctx, U0, dx, nsteps, cfl, ckpt_every, bc):
+        prm = api.params("euler", bc=bc)
+        UT, dts, als, ckpts = forward_checkpointed(U0.detach().contiguous(), dx, nsteps, cfl,
+                                                   prm, ckpt_every)
+        ctx.save_for_backward(dts, als, *ckpts)
+        ctx.cfg = (dx, ckpt_every, bc)
+        return UT
+
+    @staticmethod
+    def backward(ctx, gUT):
+        dts, als, *ckpts = ctx.saved_tensors
+        dx, ckpt_every, bc = ctx.cfg
+        lam0 = backward_checkpointed(gUT.contiguous(), dx, dts, als, ckpts, ckpt_every,
+                                     api.params("euler", bc=bc))
+        return lam0, None, None, None, None, None

@@ -229,3 +229,32 @@ def batched_rk3_run_1d(u, offsets, dx, nsteps, cfl=0.5, prm=None, order=None, tu
                                        float(cfl), C.byref(tn) if tn is not None else None,
                                        _ptr(dt_o), _ptr(workspace(u.device)), _stream()))
     return dt_o
+
+
+def rhs_1d_vjp(u, mu, dx, prm=None, out=None):
+    """J(u)^T mu for the 1D Euler right-hand side, alpha frozen (prm.lf_alpha_x if >= 0, else
+    max(|u| + c) of u held constant)."""
+    prm = prm or params("euler")
+    _check_state(u, 3)
+    _check_state(mu, 3, "mu")
+    out = torch.empty_like(u) if out is None else out
+    check(lib().wzn_rhs_1d_vjp(C.byref(prm), _ptr(u), _ptr(mu), _ptr(out), u.shape[1], float(dx),
+                               _ptr(workspace(u.device)), _stream()))
+    return out
+
+
+def rk3_step_1d_vjp(stages, lam_next, dt, alpha3, dx, prm=None, out=None, scratch=None):
+    """(dU^{n+1}/dU^n)^T lam_next for one TVD-RK3 step with frozen dt and stage alphas.
+    stages: [3, 3, n] (U^n, U1, U2); dt: device tensor (1 element); alpha3: device [3]."""
+    prm = prm or params("euler")
+    if stages.dim() != 3 or stages.shape[0] != 3 or not stages.is_contiguous():
+        raise ValueError("stages must be a contiguous [3, 3, n] tensor")
+    _check_state(lam_next, 3, "lam_next")
+    n = lam_next.shape[1]
+    out = torch.empty_like(lam_next) if out is None else out
+    scratch = torch.empty((3, 3, n), dtype=torch.float64, device=lam_next.device) \
+        if scratch is None else scratch
+    check(lib().wzn_rk3_step_1d_vjp(C.byref(prm), _ptr(stages), _ptr(lam_next), _ptr(out),
+                                    _ptr(scratch), n, float(dx), _ptr(dt), _ptr(alpha3),
+                                    _ptr(workspace(lam_next.device)), _stream()))
+    return out

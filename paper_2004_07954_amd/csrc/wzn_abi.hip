@@ -232,4 +232,33 @@ int32_t wzn_batched_rk3_run_1d(const wzn_params* p, void* u, void* stage, int64_
                             nsteps, cfl, tuning, dt_out, &w, (hipStream_t)stream);
 }
 
+int32_t wzn_rhs_1d_vjp(const wzn_params* p, const void* u, const void* mu, void* out, int64_t n,
+                       double dx, void* ws, void* stream) {
+  g_err[0] = 0;
+  int st = check_1d(p, n, dx, ws);
+  if (st) return st;
+  if (p->system != WZN_EULER) return set_error(WZN_ERR_ARG, "the adjoint is for 1D Euler");
+  if (!u || !mu || !out) return set_error(WZN_ERR_ARG, "NULL array argument");
+  if (out == u || out == mu) return set_error(WZN_ERR_ARG, "out must not alias u or mu");
+  Workspace w = make_workspace(ws);
+  return rhs_1d_vjp(p, (const double*)u, (const double*)mu, (double*)out, n, dx, &w,
+                    (hipStream_t)stream);
+}
+
+int32_t wzn_rk3_step_1d_vjp(const wzn_params* p, const void* stages, const void* lam_next,
+                            void* lam_prev, void* scratch, int64_t n, double dx,
+                            const double* dt, const double* alpha3, void* ws, void* stream) {
+  g_err[0] = 0;
+  int st = check_1d(p, n, dx, ws);
+  if (st) return st;
+  if (p->system != WZN_EULER) return set_error(WZN_ERR_ARG, "the adjoint is for 1D Euler");
+  if (!stages || !lam_next || !lam_prev || !scratch || !dt || !alpha3)
+    return set_error(WZN_ERR_ARG, "NULL argument");
+  if (lam_prev == lam_next || lam_prev == stages || lam_prev == scratch)
+    return set_error(WZN_ERR_ARG, "lam_prev must not alias the other arrays");
+  Workspace w = make_workspace(ws);
+  return rk3_step_1d_vjp(p, (const double*)stages, (const double*)lam_next, (double*)lam_prev,
+                         (double*)scratch, n, dx, dt, alpha3, &w, (hipStream_t)stream);
+}
+
 }  // extern "C"

@@ -58,6 +58,12 @@ int batched_rk3_run_1d(const wzn_params* p, double* u, double* stage, int64_t to
                        int32_t batch, int32_t nsteps, double cfl, const wzn_batch_tuning* tn,
                        double* dt_out, Workspace* ws, hipStream_t s);
 
+int rhs_1d_vjp(const wzn_params* p, const double* u, const double* mu, double* out, int64_t n,
+               double dx, Workspace* ws, hipStream_t s);
+int rk3_step_1d_vjp(const wzn_params* p, const double* stages, const double* lam_next,
+                    double* lam_prev, double* scratch, int64_t n, double dx, const double* dt,
+                    const double* alpha3, Workspace* ws, hipStream_t s);
+
 int rhs_1d(const wzn_params* p, const double* u, double* dudt, int64_t n, double dx,
            Workspace* ws, hipStream_t s);
 int rk3_run_1d(const wzn_params* p, double* u, double* stage, int64_t n, double dx, double cfl,

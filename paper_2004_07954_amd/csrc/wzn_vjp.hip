@@ -1,0 +1,317 @@
+// Hand-written discrete adjoint of the 1D WENO-ZN right-hand side and of the TVD-RK3 step.
+//
+// The map differentiated is the one the forward kernels evaluate, with the Lax-Friedrichs
+// alpha of every stage and the dt of every step frozen (they are recorded by the forward run
+// and treated as constants).  For L_i = -(fhat_{i+1/2} - fhat_{i-1/2}) / dx (Sec. 2, eq:2) the
+// cotangent of interface flux fhat_{e+1/2} is nu_e = (mu_{e+1} - mu_e) / dx; it is pulled back
+// through the two reconstructions of that interface (f^+ stencil, and the f^- stencil
+// mirrored about x_{e+1/2}), through the Lax-Friedrichs split f^{+-} = (F(U) +- alpha U)/2
+// and the Euler flux Jacobian, and through the boundary index map (ghost cells add their
+// cotangent to the cell they copy).
+//
+// One workgroup owns a tile of NT output cells.  It stages the split fluxes of the cells
+// the tile's interfaces read (tile +- 5 cells) and the cotangents mu (tile -3 .. +2) in LDS,
+// computes per interface the ten scaled partial derivatives nu_e * d fhat_e / d f^{+-}(cell),
+// and each output cell then gathers the partials of the (at most six) interfaces whose
+// stencils contain it.
+//
+// Stage adjoint (fused): with v = mu + dt J(U_s)^T mu,
+//   out = p v + q acc_in,   acc_out = r acc_in + s mu
+// which covers the three stages of the TVD-RK3 adjoint recurrence
+//   lam2 = 2/3 (lam3 + dt J2^T lam3),        acc = 1/3 lam3
+//   lam1 = 1/4 (lam2 + dt J1^T lam2),        acc = acc + 3/4 lam2
+//   lam0 = acc + lam1 + dt J0^T lam1.
+#include <hip/hip_runtime.h>
+
+#include "wzn_device.hpp"
+#include "wzn_host.hpp"
+#include "wzn_rows.hpp"
+#include "wzn_tile.hpp"
+
+namespace wzn {
+
+struct VjpArgs {
+  const double* U;       // stage state [3][n] at which L is linearised
+  const double* mu;      // cotangent of L (or of the stage output) [3][n]
+  const double* acc_in;  // [3][n] or null
+  double* out;           // [3][n]
+  double* acc_out;       // [3][n] or null; may alias acc_in (same element, same thread)
+  int64_t n;
+  double dx;
+  int bc;
+  double gamma, eps, A;
+  const double* alpha_arr;  // frozen alpha (device) or null
+  double alpha_const;
+  const double* dt_arr;     // frozen dt (device) or null (plain VJP)
+  int stage_mode;           // 0: out = J^T mu; 1: fused stage adjoint
+  double p, q, r, s;
+};
+
+// f-hat of one reconstruction (Sec. 2.1 eq:3-5, Sec. 3 eq:function, eq:tau8, eq:new) and
+// g[k] = nu * d fhat / d v[k], evaluated in the paper's literal form (fp64 carries the
+// magnitudes of C and tau8/(IS_k+eps) for eps = 1e-40).  d|x|/dx is taken as 0 at x = 0.
+__device__ __forceinline__ void wzn_grad(const double* v, double nu, double eps, double A,
+                                         double* g) {
+  const double a = v[0], b = v[1], c = v[2], d = v[3], e = v[4];
+  const double A0 = a - 2.0 * b + c, B0 = a - 4.0 * b + 3.0 * c;
+  const double A1 = b - 2.0 * c + d, B1 = b - d;
+  const double A2 = c - 2.0 * d + e, B2 = 3.0 * c - 4.0 * d + e;
+  const double IS0 = (13.0 / 12.0) * A0 * A0 + 0.25 * B0 * B0;
+  const double IS1 = (13.0 / 12.0) * A1 * A1 + 0.25 * B1 * B1;
+  const double IS2 = (13.0 / 12.0) * A2 * A2 + 0.25 * B2 * B2;
+  const double d4 = a - 4.0 * b + 6.0 * c - 4.0 * d + e;
+  const double tau8 = d4 * d4;
+  const double diff = IS0 - IS2;
+  const double t5 = __builtin_fabs(diff);
+  const double num = IS0 + IS2 - t5 + eps, den = t5 + eps;
+  const double r = num / den;
+  const double C = A * r * r;
+  const double ck[3] = {0.1, 0.6, 0.3};
+  const double s[3] = {IS0 + eps, IS1 + eps, IS2 + eps};
+  double t[3], al[3];
+  double S = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    t[k] = tau8 / s[k];
+    al[k] = ck[k] * (C + t[k]);
+    S += al[k];
+  }
+  const double q[3] = {(2.0 * a - 7.0 * b + 11.0 * c) / 6.0, (-b + 5.0 * c + 2.0 * d) / 6.0,
+                       (2.0 * c + 5.0 * d - e) / 6.0};
+  double om[3], fh = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    om[k] = al[k] / S;
+    fh += om[k] * q[k];
+  }
+  // reverse sweep
+  double Cb = 0.0, tau8b = 0.0, sb[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double alb = nu * (q[k] - fh) / S;
+    const double tb = ck[k] * alb;
+    Cb += tb;
+    tau8b += tb / s[k];
+    sb[k] = -tb * t[k] / s[k];
+  }
+  const double rb = Cb * 2.0 * A * r;
+  const double numb = rb / den;
+  const double denb = -rb * r / den;
+  double IS0b = sb[0] + numb, IS1b = sb[1], IS2b = sb[2] + numb;
+  const double t5b = -numb + denb;
+  const double sg = diff > 0.0 ? 1.0 : (diff < 0.0 ? -1.0 : 0.0);
+  IS0b += sg * t5b;
+  IS2b -= sg * t5b;
+  const double d4b = 2.0 * d4 * tau8b;
+  const double A0b = (13.0 / 6.0) * A0 * IS0b, B0b = 0.5 * B0 * IS0b;
+  const double A1b = (13.0 / 6.0) * A1 * IS1b, B1b = 0.5 * B1 * IS1b;
+  const double A2b = (13.0 / 6.0) * A2 * IS2b, B2b = 0.5 * B2 * IS2b;
+  const double qb0 = nu * om[0], qb1 = nu * om[1], qb2 = nu * om[2];
+  g[0] = d4b + A0b + B0b + qb0 / 3.0;
+  g[1] = -4.0 * d4b - 2.0 * A0b - 4.0 * B0b + A1b + B1b - qb0 * (7.0 / 6.0) - qb1 / 6.0;
+  g[2] = 6.0 * d4b + A0b + 3.0 * B0b - 2.0 * A1b + A2b + 3.0 * B2b + qb0 * (11.0 / 6.0) +
+         qb1 * (5.0 / 6.0) + qb2 / 3.0;
+  g[3] = -4.0 * d4b + A1b - B1b - 2.0 * A2b - 4.0 * B2b + qb1 / 3.0 + qb2 * (5.0 / 6.0);
+  g[4] = d4b + A2b + B2b - qb2 / 6.0;
+}
+
+__device__ __forceinline__ int64_t map_cell(int64_t p, int64_t n, int bc) {
+  if (bc == 0) {
+    p %= n;
+    return p < 0 ? p + n : p;
+  }
+  return p < 0 ? 0 : (p >= n ? n - 1 : p);
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void vjp_kernel(VjpArgs a) {
+  constexpr int NW = NT + 10;  // staged split-flux cells: g0-5 .. g0+NT+4
+  constexpr int NM = NT + 6;   // staged cotangent cells:  g0-3 .. g0+NT+2
+  constexpr int NI = NT + 5;   // interfaces (right interface of cell e): e = g0-3 .. g0+NT+1
+  __shared__ double Wp[3][NW], Wm[3][NW], MU[3][NM], G[10][NI];
+  const int tid = threadIdx.x;
+  const int64_t n = a.n;
+  const int64_t g0 = (int64_t)blockIdx.x * NT;
+  const double alpha = a.alpha_arr ? a.alpha_arr[0] : a.alpha_const;
+  const double gm1 = a.gamma - 1.0;
+
+  for (int i = tid; i < NW; i += NT) {
+    const int64_t cell = map_cell(g0 - 5 + i, n, a.bc);
+    const double rho = a.U[cell], m = a.U[n + cell], E = a.U[2 * n + cell];
+    const double u = m / rho;
+    const double p = gm1 * (E - 0.5 * rho * u * u);
+    const double F[3] = {rho * u, rho * u * u + p, u * (E + p)};
+    const double Uc[3] = {rho, m, E};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      Wp[c][i] = 0.5 * (F[c] + alpha * Uc[c]);
+      Wm[c][i] = 0.5 * (F[c] - alpha * Uc[c]);
+    }
+  }
+  for (int i = tid; i < NM; i += NT) {
+    const int64_t cell = g0 - 3 + i;
+    int64_t src = -1;
+    if (a.bc == 0) src = map_cell(cell, n, 0);
+    else if (cell >= 0 && cell < n) src = cell;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) MU[c][i] = src >= 0 ? a.mu[c * n + src] : 0.0;
+  }
+  __syncthreads();
+
+  const int64_t j = g0 + tid;  // this thread's output cell
+  double wbp[3] = {0.0, 0.0, 0.0}, wbm[3] = {0.0, 0.0, 0.0};
+  for (int c = 0; c < 3; ++c) {
+    for (int i = tid; i < NI; i += NT) {
+      const int64_t e = g0 - 3 + i;
+      const bool valid = a.bc == 0 || (e >= -1 && e <= n - 1);
+      const double nu = valid ? (MU[c][i + 1] - MU[c][i]) / a.dx : 0.0;
+      double v[5], gp[5], gmv[5];
+#pragma unroll
+      for (int k = 0; k < 5; ++k) v[k] = Wp[c][i + k];          // cells e-2 .. e+2
+      wzn_grad(v, nu, a.eps, a.A, gp);
+#pragma unroll
+      for (int k = 0; k < 5; ++k) v[k] = Wm[c][i + 5 - k];      // cells e+3 .. e-1
+      wzn_grad(v, nu, a.eps, a.A, gmv);
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        G[k][i] = gp[k];
+        G[5 + k][i] = gmv[k];
+      }
+    }
+    __syncthreads();
+    if (j < n) {
+      double sp = 0.0, sm = 0.0;
+      for (int de = -3; de <= 2; ++de) {
+        const int64_t e = j + de;
+        const int i = (int)(e - (g0 - 3));
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+          if (map_cell(e - 2 + k, n, a.bc) == j) sp += G[k][i];
+          if (map_cell(e + 3 - k, n, a.bc) == j) sm += G[5 + k][i];
+        }
+      }
+      wbp[c] = sp;
+      wbm[c] = sm;
+    }
+    __syncthreads();
+  }
+  if (j >= n) return;
+
+  // f^{+-}_c = (F_c +- alpha U_c)/2:  Ubar_d = 1/2 sum_c (wbp_c + wbm_c) dF_c/dU_d
+  //                                          + alpha/2 (wbp_d - wbm_d)
+  const double rho = a.U[j], m = a.U[n + j], E = a.U[2 * n + j];
+  const double u = m / rho;
+  const double p = gm1 * (E - 0.5 * rho * u * u);
+  const double H = (E + p) / rho;
+  // Jacobian of F = (m, m^2/rho + p, u (E + p)) with p = (gamma-1)(E - m^2/(2 rho))
+  const double J[3][3] = {
+      {0.0, 1.0, 0.0},
+      {0.5 * (a.gamma - 3.0) * u * u, (3.0 - a.gamma) * u, gm1},
+      {u * (0.5 * gm1 * u * u - H), H - gm1 * u * u, a.gamma * u}};
+  double Ub[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    double acc = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc += (wbp[c] + wbm[c]) * J[c][d];
+    Ub[d] = 0.5 * acc + 0.5 * alpha * (wbp[d] - wbm[d]);
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const int64_t gi = c * n + j;
+    if (a.stage_mode == 0) {
+      a.out[gi] = Ub[c];
+    } else {
+      const double dt = a.dt_arr[0];
+      const double mu_j = a.mu[gi];
+      const double v = mu_j + dt * Ub[c];
+      const double ain = a.acc_in ? a.acc_in[gi] : 0.0;
+      a.out[gi] = a.p * v + a.q * ain;
+      if (a.acc_out) a.acc_out[gi] = a.r * ain + a.s * mu_j;
+    }
+  }
+}
+
+static int launch_vjp(const VjpArgs& a, hipStream_t s) {
+  constexpr int NT = 256;
+  const int64_t blocks = (a.n + NT - 1) / NT;
+  if (blocks > 0x7fffffff) return set_error(WZN_ERR_SIZE, "grid too large (vjp)");
+  hipLaunchKernelGGL((vjp_kernel<NT>), dim3((unsigned)blocks), dim3(NT), 0, s, a);
+  return check_launch("vjp_kernel");
+}
+
+static VjpArgs vjp_base(const wzn_params* p, int64_t n, double dx) {
+  VjpArgs a{};
+  a.n = n;
+  a.dx = dx;
+  a.bc = p->bc_x;
+  a.gamma = p->gamma;
+  a.eps = p->eps;
+  a.A = p->A;
+  return a;
+}
+
+int rhs_1d_vjp(const wzn_params* p, const double* u, const double* mu, double* out, int64_t n,
+               double dx, Workspace* ws, hipStream_t s) {
+  VjpArgs a = vjp_base(p, n, dx);
+  a.U = u;
+  a.mu = mu;
+  a.out = out;
+  if (p->lf_alpha_x >= 0.0) {
+    a.alpha_const = p->lf_alpha_x;
+  } else {
+    int st = launch_zero_words(ws->speed, 1, s);
+    if (st) return st;
+    st = launch_speed_max<double>(u, n, 3, p->gamma, ws->speed, nullptr, s);
+    if (st) return st;
+    a.alpha_arr = (const double*)ws->speed;  // the max, frozen
+  }
+  return launch_vjp(a, s);
+}
+
+int rk3_step_1d_vjp(const wzn_params* p, const double* stages, const double* lam_next,
+                    double* lam_prev, double* scratch, int64_t n, double dx, const double* dt,
+                    const double* alpha3, Workspace* ws, hipStream_t s) {
+  (void)ws;
+  const int64_t M = 3 * n;
+  const double* U0 = stages;
+  const double* U1 = stages + M;
+  const double* U2 = stages + 2 * M;
+  double* lam2 = scratch;
+  double* lam1 = scratch + M;
+  double* acc = scratch + 2 * M;
+  // stage 3: lam2 = 2/3 (lam3 + dt J2^T lam3); acc = 1/3 lam3
+  VjpArgs a = vjp_base(p, n, dx);
+  a.stage_mode = 1;
+  a.dt_arr = dt;
+  a.U = U2;
+  a.mu = lam_next;
+  a.alpha_arr = alpha3 + 2;
+  a.out = lam2;
+  a.acc_in = nullptr;
+  a.acc_out = acc;
+  a.p = 2.0 / 3.0; a.q = 0.0; a.r = 0.0; a.s = 1.0 / 3.0;
+  int st = launch_vjp(a, s);
+  if (st) return st;
+  // stage 2: lam1 = 1/4 (lam2 + dt J1^T lam2); acc += 3/4 lam2
+  a.U = U1;
+  a.mu = lam2;
+  a.alpha_arr = alpha3 + 1;
+  a.out = lam1;
+  a.acc_in = acc;
+  a.acc_out = acc;
+  a.p = 0.25; a.q = 0.0; a.r = 1.0; a.s = 0.75;
+  st = launch_vjp(a, s);
+  if (st) return st;
+  // stage 1: lam0 = acc + lam1 + dt J0^T lam1
+  a.U = U0;
+  a.mu = lam1;
+  a.alpha_arr = alpha3;
+  a.out = lam_prev;
+  a.acc_in = acc;
+  a.acc_out = nullptr;
+  a.p = 1.0; a.q = 1.0; a.r = 0.0; a.s = 0.0;
+  return launch_vjp(a, s);
+}
+
+}  // namespace wzn

@@ -1,0 +1,193 @@
+"""GPU checks of the hand-written discrete adjoint (1D Euler, frozen dt and alphas).
+
+References: Jacobians and directional derivatives from the CPU oracle's complex-step path
+(independent of the GPU code, pinned in test_oracle_adjoint.py), and central finite
+differences of the GPU forward run.
+"""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2004_07954_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+VJP_TOL = 1e-10
+BC = {"periodic": 0, "transmissive": 1}
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2004_07954_amd import api
+    return api
+
+
+def note(*args):
+    print("[gpu-case]", *args, flush=True)
+
+
+def to_dev(x):
+    import torch
+    return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def normwise(gpu, ref):
+    return max(np.abs(gpu[c] - ref[c]).max() / max(np.abs(ref[c]).max(), 1e-300)
+               for c in range(ref.shape[0]))
+
+
+def cs_jacobian(fn, u, h=1e-30):
+    """Full Jacobian of fn (a map of [3, n] states) by the complex step, column by column."""
+    nv, n = u.shape
+    Jm = np.zeros((nv * n, nv * n))
+    for c in range(nv):
+        for i in range(n):
+            z = u.astype(complex)
+            z[c, i] += 1j * h
+            Jm[:, c * n + i] = (fn(z).imag / h).reshape(-1)
+    return Jm
+
+
+@pytest.mark.parametrize("bc", ["periodic", "transmissive"])
+def test_rhs_vjp_against_complex_step(api, orc, bc):
+    note("rhs vjp vs complex step", bc)
+    n = 40
+    u = I.random_smooth_1d(n, seed=61)
+    if bc == "transmissive":
+        u[:, n // 2:] *= 1.7  # a jump
+    alpha = 2.75
+    Jm = cs_jacobian(lambda z: orc.rhs_1d_complex(z, 0.03, alpha, bc=BC[bc]), u)
+    mu = np.random.default_rng(62).standard_normal(u.shape)
+    ref = (Jm.T @ mu.reshape(-1)).reshape(u.shape)
+    g = api.rhs_1d_vjp(to_dev(u), to_dev(mu), 0.03, api.params("euler", bc=bc, lf_alpha=alpha))
+    assert normwise(g.cpu().numpy(), ref) <= VJP_TOL
+
+
+def test_rhs_vjp_ragged_tiles(api, orc):
+    """Several tiles and a ragged tail (n = 700), against J^T mu assembled from the oracle's
+    complex-step Jacobian restricted to its band (columns coloured mod 16)."""
+    note("rhs vjp n=700")
+    n = 700
+    u = I.random_smooth_1d(n, seed=63)
+    alpha = 2.5
+    mu = np.random.default_rng(64).standard_normal(u.shape)
+    ref = np.zeros_like(u)
+    h = 1e-30
+    for c in range(3):
+        for col in range(14):  # cells j = col mod 14; stencils reach 7 cells, n % 14 == 0
+            z = u.astype(complex)
+            z[c, col::14] += 1j * h
+            d = orc.rhs_1d_complex(z, 0.01, alpha, bc=0).imag / h  # [3, n] sum of columns
+            for j in range(col, n, 14):
+                # rows i within 3 cells of j (periodic) belong to column j
+                rows = [(j + k) % n for k in range(-3, 4)]
+                ref[c, j] += sum(d[cc, r] * mu[cc, r] for cc in range(3) for r in rows)
+    g = api.rhs_1d_vjp(to_dev(u), to_dev(mu), 0.01, api.params("euler", bc="periodic",
+                                                               lf_alpha=alpha))
+    assert normwise(g.cpu().numpy(), ref) <= VJP_TOL
+
+
+@pytest.mark.parametrize("bc", ["periodic", "transmissive"])
+def test_step_vjp_against_complex_step(api, orc, bc):
+    import torch
+    note("rk3 step vjp vs complex step", bc)
+    n = 36
+    u = I.random_smooth_1d(n, seed=65)
+    un, dt, al3 = orc.rk3_step_1d(u, 0.02, cfl=0.5, bc=BC[bc])
+    Jm = cs_jacobian(lambda z: orc.rk3_step_1d_complex(z, 0.02, dt, al3, bc=BC[bc]), u)
+    lam = np.random.default_rng(66).standard_normal(u.shape)
+    ref = (Jm.T @ lam.reshape(-1)).reshape(u.shape)
+    # GPU stage states with the same frozen schedule
+    prm = api.params("euler", bc=bc)
+    stages = torch.empty((3, 3, n), dtype=torch.float64, device="cuda")
+    stages[0].copy_(to_dev(u))
+    U = to_dev(u)
+    dtt, alt = to_dev([dt]), to_dev(al3)
+    api.rk3_run_1d(U, 0.02, 1, dt=dtt, alpha=alt.view(1, 3), prm=prm, stage=stages[1:3])
+    out = api.rk3_step_1d_vjp(stages, to_dev(lam), dtt, alt, 0.02, prm=prm)
+    assert normwise(out.cpu().numpy(), ref) <= VJP_TOL
+
+
+def _c5_like(n, seed=5):
+    u0, ut, dx = I.adjoint_case(n=n, seed=seed, sigma_cells=max(4.0, 256.0 * n / 65536))
+    return u0, ut, dx
+
+
+def _loss_and_grad(api, rho0, rho_t, dx, nsteps, ckpt):
+    """L = 1/2 ||rho_T - rho_target||^2 with U0 = (rho0, 0.5 rho0, 1/(g-1) + rho0/8)."""
+    import torch
+    from paper_2004_07954_amd.adjoint import WenoZNRK3
+    r0 = rho0.clone().requires_grad_(True)
+    U0 = torch.stack([r0, 0.5 * r0, 1.0 / 0.4 + 0.125 * r0])
+    UT = WenoZNRK3.apply(U0, dx, nsteps, 0.5, ckpt, "periodic")
+    L = 0.5 * ((UT[0] - rho_t) ** 2).sum()
+    L.backward()
+    return L.detach(), r0.grad.detach()
+
+
+def test_adjoint_chain_against_complex_step(api, orc):
+    """N = 256, 40 steps, checkpoints every 20: <grad, v> for 6 random directions against the
+    complex-step directional derivative of the oracle's run with the same frozen schedule."""
+    import torch
+    from paper_2004_07954_amd import adjoint
+    note("adjoint chain N=256 x40")
+    n, nsteps = 256, 40
+    u0, ut, dx = _c5_like(n)
+    rho_t = torch.tensor(ut[0], dtype=torch.float64, device="cuda")
+    rho0 = torch.tensor(u0[0], dtype=torch.float64, device="cuda")
+    _, g = _loss_and_grad(api, rho0, rho_t, dx, nsteps, 20)
+    # the schedule the forward recorded
+    U0 = torch.tensor(u0, dtype=torch.float64, device="cuda")
+    _, dts, als, _ = adjoint.forward_checkpointed(U0, dx, nsteps, 0.5,
+                                                  api.params("euler", bc="periodic"), 20)
+    dts, als = dts.cpu().numpy(), als.cpu().numpy()
+    g = g.cpu().numpy()
+    rng = np.random.default_rng(67)
+    for _ in range(6):
+        v = rng.standard_normal(n)
+        h = 1e-30
+        z = np.stack([u0[0] + 1j * h * v, 0.5 * (u0[0] + 1j * h * v),
+                      1.0 / 0.4 + 0.125 * (u0[0] + 1j * h * v)])
+        for t in range(nsteps):
+            z = orc.rk3_step_1d_complex(z, dx, dts[t], als[t], bc=0)
+        dL = np.sum((z[0].real - ut[0]) * z[0].imag / h)
+        assert abs(g @ v - dL) <= 1e-8 * abs(dL), (g @ v, dL)
+
+
+def test_adjoint_c5_finite_differences_and_cost(api):
+    """The adjoint workload: N = 65536 periodic, 400 steps, checkpoints every 20.  Central
+    finite differences of the loss along 64 random unit directions (frozen schedule, h swept
+    over 1e-2 .. 1e-7) agree with <grad, v> to 1e-6 relative at the best h; the backward pass
+    (recompute + adjoint) time is reported against the forward time."""
+    import torch
+    from paper_2004_07954_amd import adjoint
+    note("adjoint C5 N=65536 x400 FD x64")
+    n, nsteps = 65536, 400
+    u0, ut, dx = _c5_like(n)
+    rho_t = torch.tensor(ut[0], dtype=torch.float64, device="cuda")
+    rho0 = torch.tensor(u0[0], dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    L, g = _loss_and_grad(api, rho0, rho_t, dx, nsteps, 20)
+    U0 = torch.tensor(u0, dtype=torch.float64, device="cuda")
+    _, dts, als, _ = adjoint.forward_checkpointed(U0, dx, nsteps, 0.5,
+                                                  api.params("euler", bc="periodic"), 20)
+
+    def loss(r):
+        U = torch.stack([r, 0.5 * r, 1.0 / 0.4 + 0.125 * r])
+        UT = adjoint.run_frozen(U, dx, dts, als)
+        return float(0.5 * ((UT[0] - rho_t) ** 2).sum())
+
+    dirs = torch.tensor(I.unit_directions(n, 64, seed=68), dtype=torch.float64, device="cuda")
+    worst = 0.0
+    for k in range(64):
+        v = dirs[k]
+        gv = float(g @ v)
+        best = np.inf
+        for h in (1e-2, 1e-3, 1e-4, 1e-5, 1e-6, 1e-7):
+            fd = (loss(rho0 + h * v) - loss(rho0 - h * v)) / (2 * h)
+            best = min(best, abs(fd - gv) / abs(gv))
+        worst = max(worst, best)
+    print("adjoint FD worst relative error over 64 directions: %.2e" % worst)
+    assert worst <= 1e-6
