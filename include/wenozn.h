@@ -192,6 +192,22 @@ int32_t wzn_rk3_step_1d_vjp(const wzn_params* p, const void* stages, const void*
                             void* lam_prev, void* scratch, int64_t n, double dx,
                             const double* dt, const double* alpha3, void* ws, void* stream);
 
+/* wzn_rk3_adjoint_1d_work_doubles: size (in doubles) of `work` for wzn_rk3_adjoint_1d. */
+int64_t wzn_rk3_adjoint_1d_work_doubles(int64_t n, int32_t ckpt_every);
+
+/* wzn_rk3_adjoint_1d: the whole reverse pass of an nsteps TVD-RK3 run with checkpointed
+ * recomputation, in one call (everything enqueued on `stream`, no host synchronisation).
+ *   ckpts    [nseg][3][n], nseg = ceil(nsteps / ckpt_every): state before steps 0,
+ *            ckpt_every, 2 ckpt_every, ... (as recorded by the forward run).
+ *   dts      device [nsteps]; alphas: device [nsteps][3] (the forward's recorded schedule).
+ *   lam      [3][n], in: dJ/dU_T; out: dJ/dU_0.
+ *   work     device scratch of wzn_rk3_adjoint_1d_work_doubles(n, ckpt_every) doubles.
+ * Per segment, last to first: the stage states of its steps are recomputed from the checkpoint
+ * with the frozen schedule, then the step adjoints of wzn_rk3_step_1d_vjp run in reverse. */
+int32_t wzn_rk3_adjoint_1d(const wzn_params* p, const void* ckpts, int32_t nsteps,
+                           int32_t ckpt_every, const double* dts, const double* alphas,
+                           void* lam, void* work, int64_t n, double dx, void* ws, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -49,6 +49,8 @@ SIGNATURES = [
                                       C.POINTER(WznBatchTuning), _P, _P, _P]),
     ("wzn_rhs_1d_vjp", _I32, [_PP, _P, _P, _P, _I64, _D, _P, _P]),
     ("wzn_rk3_step_1d_vjp", _I32, [_PP, _P, _P, _P, _P, _I64, _D, _P, _P, _P, _P]),
+    ("wzn_rk3_adjoint_1d_work_doubles", _I64, [_I64, _I32]),
+    ("wzn_rk3_adjoint_1d", _I32, [_PP, _P, _I32, _I32, _P, _P, _P, _P, _I64, _D, _P, _P]),
 ]
 
 _LIB = None

@@ -40,31 +40,24 @@ def run_frozen(U0, dx, dts, als, prm=None):
     return U
 
 
-def backward_checkpointed(lamT, dx, dts, als, ckpts, ckpt_every=20, prm=None):
-    """lam_0 = (dU_T/dU_0)^T lam_T with the frozen schedule."""
+def backward_checkpointed(lamT, dx, dts, als, ckpts, ckpt_every=20, prm=None, work=None):
+    """lam_0 = (dU_T/dU_0)^T lam_T with the frozen schedule: one library call that enqueues
+    the recomputation of every segment and the step adjoints in reverse."""
+    import ctypes as C
+    from ._lib import check, lib
     prm = prm or api.params("euler", bc="periodic")
     nsteps = dts.numel()
     n = lamT.shape[1]
-    dev = lamT.device
-    lam = lamT.clone()
-    lam_prev = torch.empty_like(lam)
-    scratch = torch.empty((3, 3, n), dtype=torch.float64, device=dev)
-    seg_stages = torch.empty((ckpt_every, 3, 3, n), dtype=torch.float64, device=dev)
-    nseg = len(ckpts)
-    for sgi in reversed(range(nseg)):
-        t0 = sgi * ckpt_every
-        steps = min(ckpt_every, nsteps - t0)
-        U = ckpts[sgi].clone()
-        for k in range(steps):
-            t = t0 + k
-            seg_stages[k, 0].copy_(U)
-            api.rk3_run_1d(U, dx, 1, dt=dts[t:t + 1], alpha=als[t:t + 1], prm=prm,
-                           stage=seg_stages[k, 1:3])
-        for k in reversed(range(steps)):
-            t = t0 + k
-            api.rk3_step_1d_vjp(seg_stages[k], lam, dts[t:t + 1], als[t], dx, prm=prm,
-                                out=lam_prev, scratch=scratch)
-            lam, lam_prev = lam_prev, lam
+    ck = ckpts if isinstance(ckpts, torch.Tensor) else torch.stack(list(ckpts))
+    ck = ck.contiguous()
+    lam = lamT.clone().contiguous()
+    need = lib().wzn_rk3_adjoint_1d_work_doubles(n, ckpt_every)
+    if work is None or work.numel() < need:
+        work = torch.empty(need, dtype=torch.float64, device=lamT.device)
+    check(lib().wzn_rk3_adjoint_1d(C.byref(prm), api._ptr(ck), int(nsteps), int(ckpt_every),
+                                   api._ptr(dts.contiguous()), api._ptr(als.contiguous()),
+                                   api._ptr(lam), api._ptr(work), n, float(dx),
+                                   api._ptr(api.workspace(lamT.device)), api._stream()))
     return lam
 
 

@@ -261,4 +261,23 @@ int32_t wzn_rk3_step_1d_vjp(const wzn_params* p, const void* stages, const void*
                          (double*)scratch, n, dx, dt, alpha3, &w, (hipStream_t)stream);
 }
 
+int64_t wzn_rk3_adjoint_1d_work_doubles(int64_t n, int32_t ckpt_every) {
+  if (n < 1 || ckpt_every < 1) return 0;
+  return ((int64_t)ckpt_every * 3 + 3) * 3 * n + 3 * n;
+}
+
+int32_t wzn_rk3_adjoint_1d(const wzn_params* p, const void* ckpts, int32_t nsteps,
+                           int32_t ckpt_every, const double* dts, const double* alphas,
+                           void* lam, void* work, int64_t n, double dx, void* ws, void* stream) {
+  g_err[0] = 0;
+  int st = check_1d(p, n, dx, ws);
+  if (st) return st;
+  if (p->system != WZN_EULER) return set_error(WZN_ERR_ARG, "the adjoint is for 1D Euler");
+  if (!ckpts || !dts || !alphas || !lam || !work) return set_error(WZN_ERR_ARG, "NULL argument");
+  if (nsteps < 0 || ckpt_every < 1) return set_error(WZN_ERR_ARG, "bad nsteps / ckpt_every");
+  Workspace w = make_workspace(ws);
+  return rk3_adjoint_1d(p, (const double*)ckpts, nsteps, ckpt_every, dts, alphas, (double*)lam,
+                        (double*)work, n, dx, &w, (hipStream_t)stream);
+}
+
 }  // extern "C"

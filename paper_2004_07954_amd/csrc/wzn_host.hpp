@@ -64,6 +64,10 @@ int rk3_step_1d_vjp(const wzn_params* p, const double* stages, const double* lam
                     double* lam_prev, double* scratch, int64_t n, double dx, const double* dt,
                     const double* alpha3, Workspace* ws, hipStream_t s);
 
+int rk3_adjoint_1d(const wzn_params* p, const double* ckpts, int32_t nsteps, int32_t ckpt_every,
+                   const double* dts, const double* alphas, double* lam, double* work,
+                   int64_t n, double dx, Workspace* ws, hipStream_t s);
+
 int rhs_1d(const wzn_params* p, const double* u, double* dudt, int64_t n, double dx,
            Workspace* ws, hipStream_t s);
 int rk3_run_1d(const wzn_params* p, double* u, double* stage, int64_t n, double dx, double cfl,

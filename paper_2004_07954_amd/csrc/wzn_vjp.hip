@@ -76,21 +76,27 @@ __device__ __forceinline__ void wzn_grad(const double* v, double nu, double eps,
     al[k] = ck[k] * (C + t[k]);
     S += al[k];
   }
-  const double q[3] = {(2.0 * a - 7.0 * b + 11.0 * c) / 6.0, (-b + 5.0 * c + 2.0 * d) / 6.0,
-                       (2.0 * c + 5.0 * d - e) / 6.0};
-  double om[3], fh = 0.0;
+  // q_k - q_1 from second differences (eq:4): no cancellation of the O(f) parts
+  const double dq[3] = {(A0 - A1) / 3.0, 0.0, (A1 - A2) / 6.0};
+  double tbar = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) tbar += ck[k] * t[k];
+  double om[3], fr = 0.0;  // fr = fhat - q_1 = sum_k omega_k (q_k - q_1)
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     om[k] = al[k] / S;
-    fh += om[k] * q[k];
+    fr += om[k] * dq[k];
   }
-  // reverse sweep
+  // reverse sweep.  omega_k - c_k = c_k (t_k - tbar) / S is formed without the (possibly huge)
+  // C, and sum_k c_k (q_k - fhat) = -sum_k (omega_k - c_k)(q_k - q_1): where C dominates,
+  // both are tiny differences that a direct evaluation would bury in rounding noise, which
+  // the 1/den of dC/dtau5 then amplifies.
   double Cb = 0.0, tau8b = 0.0, sb[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    const double alb = nu * (q[k] - fh) / S;
-    const double tb = ck[k] * alb;
-    Cb += tb;
+    const double wk = ck[k] * (t[k] - tbar) / S;
+    Cb -= nu * wk * dq[k] / S;
+    const double tb = ck[k] * nu * (dq[k] - fr) / S;  // c_k * dL/dalpha_k
     tau8b += tb / s[k];
     sb[k] = -tb * t[k] / s[k];
   }
@@ -115,12 +121,15 @@ __device__ __forceinline__ void wzn_grad(const double* v, double nu, double eps,
   g[4] = d4b + A2b + B2b - qb2 / 6.0;
 }
 
+// Boundary index map: periodic wrap or transmissive clamp of any cell index p (the integer
+// division only runs for indices outside the grid).
 __device__ __forceinline__ int64_t map_cell(int64_t p, int64_t n, int bc) {
+  if (p >= 0 && p < n) return p;
   if (bc == 0) {
     p %= n;
     return p < 0 ? p + n : p;
   }
-  return p < 0 ? 0 : (p >= n ? n - 1 : p);
+  return p < 0 ? 0 : n - 1;
 }
 
 template <int NT>
@@ -181,13 +190,24 @@ __global__ __launch_bounds__(NT) void vjp_kernel(VjpArgs a) {
     __syncthreads();
     if (j < n) {
       double sp = 0.0, sm = 0.0;
-      for (int de = -3; de <= 2; ++de) {
-        const int64_t e = j + de;
-        const int i = (int)(e - (g0 - 3));
+      const int base = (int)(j - (g0 - 3));  // interface slot of e = j
+      if (j >= 5 && j + 5 < n) {
+        // interior: cell j is slot k = j - e + 2 of the f^+ stencil of interface e and slot
+        // k = e + 3 - j of the f^- stencil
 #pragma unroll
-        for (int k = 0; k < 5; ++k) {
-          if (map_cell(e - 2 + k, n, a.bc) == j) sp += G[k][i];
-          if (map_cell(e + 3 - k, n, a.bc) == j) sm += G[5 + k][i];
+        for (int de = -3; de <= 2; ++de) {
+          if (de >= -2) sp += G[2 - de][base + de];
+          if (de <= 1) sm += G[5 + 3 + de][base + de];
+        }
+      } else {
+#pragma unroll
+        for (int de = -3; de <= 2; ++de) {
+          const int64_t e = j + de;
+#pragma unroll
+          for (int k = 0; k < 5; ++k) {
+            if (map_cell(e - 2 + k, n, a.bc) == j) sp += G[k][base + de];
+            if (map_cell(e + 3 - k, n, a.bc) == j) sm += G[5 + k][base + de];
+          }
         }
       }
       wbp[c] = sp;
@@ -312,6 +332,81 @@ int rk3_step_1d_vjp(const wzn_params* p, const double* stages, const double* lam
   a.acc_out = nullptr;
   a.p = 1.0; a.q = 1.0; a.r = 0.0; a.s = 0.0;
   return launch_vjp(a, s);
+}
+
+// Three stage launches of one TVD-RK3 step with a frozen schedule, reading U^n from `uin`
+// and writing U1, U2 and (unless uout is null) U^{n+1} to separate arrays.
+static int frozen_step(const wzn_params* p, const double* uin, double* U1, double* U2,
+                       double* uout, int64_t n, double dx, const double* dt,
+                       const double* alpha3, hipStream_t s) {
+  const double ra[3] = {0.0, 3.0 / 4.0, 1.0 / 3.0};
+  const double rb[3] = {1.0, 1.0 / 4.0, 2.0 / 3.0};
+  for (int k = 0; k < 3; ++k) {
+    if (k == 2 && !uout) break;
+    RowArgs<double> a{};
+    a.n = n;
+    a.plane = n;
+    a.dx = dx;
+    a.bc = p->bc_x;
+    a.gamma = p->gamma;
+    a.eps_s = 16.0 * p->eps;
+    a.A = p->A;
+    a.mode = MODE_STAGE;
+    a.uin = k == 0 ? uin : (k == 1 ? U1 : U2);
+    a.out = k == 0 ? U1 : (k == 1 ? U2 : uout);
+    a.un = k == 0 ? nullptr : uin;
+    a.rk_a = ra[k];
+    a.rk_b = rb[k];
+    a.alpha_arr = alpha3 + k;
+    a.dt_arr = dt;
+    int st = launch_rows(a, SYS_EULER1, 1, tuning_1d(3, n), s);
+    if (st) return st;
+  }
+  return WZN_OK;
+}
+
+int rk3_adjoint_1d(const wzn_params* p, const double* ckpts, int32_t nsteps, int32_t ckpt_every,
+                   const double* dts, const double* alphas, double* lam, double* work,
+                   int64_t n, double dx, Workspace* ws, hipStream_t s) {
+  const int64_t M = 3 * n;
+  double* seg = work;                                  // [ckpt_every][3][M]
+  double* scratch = work + (int64_t)ckpt_every * 3 * M;  // [3][M]
+  double* lam_b = scratch + 3 * M;                     // [M]
+  const int32_t nseg = (nsteps + ckpt_every - 1) / ckpt_every;
+  double* cur = lam;
+  double* other = lam_b;
+  for (int32_t sg = nseg - 1; sg >= 0; --sg) {
+    const int32_t t0 = sg * ckpt_every;
+    const int32_t steps = nsteps - t0 < ckpt_every ? nsteps - t0 : ckpt_every;
+    // recompute the stage states of the segment from its checkpoint
+    for (int32_t k = 0; k < steps; ++k) {
+      const double* uin = k == 0 ? ckpts + (int64_t)sg * M : seg + (int64_t)k * 3 * M;
+      double* st_k = seg + (int64_t)k * 3 * M;
+      double* uout = k + 1 < steps ? seg + (int64_t)(k + 1) * 3 * M : nullptr;
+      if (k == 0) {
+        if (hipMemcpyAsync(st_k, uin, sizeof(double) * M, hipMemcpyDeviceToDevice, s) !=
+            hipSuccess)
+          return set_error(WZN_ERR_HIP, "hipMemcpyAsync (checkpoint) failed");
+      }
+      int st = frozen_step(p, st_k, st_k + M, st_k + 2 * M, uout, n, dx, dts + t0 + k,
+                           alphas + 3 * (int64_t)(t0 + k), s);
+      if (st) return st;
+    }
+    // adjoint of the segment's steps, last to first
+    for (int32_t k = steps - 1; k >= 0; --k) {
+      int st = rk3_step_1d_vjp(p, seg + (int64_t)k * 3 * M, cur, other, scratch, n, dx,
+                               dts + t0 + k, alphas + 3 * (int64_t)(t0 + k), ws, s);
+      if (st) return st;
+      double* tmp = cur;
+      cur = other;
+      other = tmp;
+    }
+  }
+  if (cur != lam) {
+    if (hipMemcpyAsync(lam, cur, sizeof(double) * M, hipMemcpyDeviceToDevice, s) != hipSuccess)
+      return set_error(WZN_ERR_HIP, "hipMemcpyAsync (adjoint result) failed");
+  }
+  return WZN_OK;
 }
 
 }  // namespace wzn

@@ -130,9 +130,14 @@ def adjoint_case(n=65536, seed=5, sigma_cells=256.0, gamma=GAMMA):
     return U0, Ut, dx
 
 
-def unit_directions(n, count, seed):
+def unit_directions(n, count, seed, smooth_cells=0.0):
+    """Random unit directions; smooth_cells > 0 applies the periodic Gaussian smoothing of
+    smoothed_noise_periodic (std in cells) before normalising."""
     rng = np.random.default_rng(seed)
-    d = rng.standard_normal((count, n))
+    if smooth_cells > 0:
+        d = np.stack([smoothed_noise_periodic(n, smooth_cells, rng) for _ in range(count)])
+    else:
+        d = rng.standard_normal((count, n))
     return d / np.linalg.norm(d, axis=1, keepdims=True)
 
 
