@@ -34,12 +34,22 @@ int launch_fill_double(double* p, double v, hipStream_t s) {
   return check_launch("fill_double_kernel");
 }
 
-static Tuning1D g_tune_euler = {256, 4};
-
+// Launch shape of the 1D row kernel: the widest tile (most sliding-window reuse) that still
+// gives >= 2048 waves (8 per CU); small grids fall back to the shape with the most waves.
 Tuning1D tuning_1d(int nv, int64_t n) {
-  (void)n;
   if (nv == 1) return Tuning1D{64, 4};
-  return g_tune_euler;
+  static const Tuning1D shapes[] = {{256, 4}, {128, 4}, {64, 4}, {64, 2}, {64, 1}};
+  Tuning1D best = shapes[0];
+  int64_t best_waves = 0;
+  for (const Tuning1D& t : shapes) {
+    const int64_t waves = (n + t.nt * t.k - 1) / (t.nt * t.k) * (t.nt / 64);
+    if (waves >= 2048) return t;
+    if (waves > best_waves) {
+      best_waves = waves;
+      best = t;
+    }
+  }
+  return best;
 }
 
 static int check_params(const wzn_params* p, bool allow_fp32) {

@@ -79,6 +79,8 @@ int launch_rows(const RowArgs<double>& a, int sys, int64_t rows, const Tuning1D&
     if (tn.nt == 128 && tn.k == 8) return launch_row_t<128, 8, SYS_EULER1, double>(a, rows, s);
     if (tn.nt == 64 && tn.k == 8) return launch_row_t<64, 8, SYS_EULER1, double>(a, rows, s);
     if (tn.nt == 64 && tn.k == 4) return launch_row_t<64, 4, SYS_EULER1, double>(a, rows, s);
+    if (tn.nt == 64 && tn.k == 2) return launch_row_t<64, 2, SYS_EULER1, double>(a, rows, s);
+    if (tn.nt == 64 && tn.k == 1) return launch_row_t<64, 1, SYS_EULER1, double>(a, rows, s);
     return set_error(WZN_ERR_ARG, "unsupported 1D tuning (nt=%d, k=%d)", tn.nt, tn.k);
   }
   if (sys == SYS_EULER2X) {

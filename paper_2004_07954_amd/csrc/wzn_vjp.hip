@@ -64,27 +64,30 @@ __device__ __forceinline__ void wzn_grad(const double* v, double nu, double eps,
   const double diff = IS0 - IS2;
   const double t5 = __builtin_fabs(diff);
   const double num = IS0 + IS2 - t5 + eps, den = t5 + eps;
-  const double r = num / den;
+  const double iden = fast_div(1.0, den);
+  const double r = num * iden;
   const double C = A * r * r;
   const double ck[3] = {0.1, 0.6, 0.3};
   const double s[3] = {IS0 + eps, IS1 + eps, IS2 + eps};
-  double t[3], al[3];
+  double is[3], t[3], al[3];
   double S = 0.0;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    t[k] = tau8 / s[k];
+    is[k] = fast_div(1.0, s[k]);
+    t[k] = tau8 * is[k];
     al[k] = ck[k] * (C + t[k]);
     S += al[k];
   }
+  const double iS = fast_div(1.0, S);
   // q_k - q_1 from second differences (eq:4): no cancellation of the O(f) parts
-  const double dq[3] = {(A0 - A1) / 3.0, 0.0, (A1 - A2) / 6.0};
+  const double dq[3] = {(A0 - A1) * (1.0 / 3.0), 0.0, (A1 - A2) * (1.0 / 6.0)};
   double tbar = 0.0;
 #pragma unroll
   for (int k = 0; k < 3; ++k) tbar += ck[k] * t[k];
   double om[3], fr = 0.0;  // fr = fhat - q_1 = sum_k omega_k (q_k - q_1)
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    om[k] = al[k] / S;
+    om[k] = al[k] * iS;
     fr += om[k] * dq[k];
   }
   // reverse sweep.  omega_k - c_k = c_k (t_k - tbar) / S is formed without the (possibly huge)
@@ -94,15 +97,15 @@ __device__ __forceinline__ void wzn_grad(const double* v, double nu, double eps,
   double Cb = 0.0, tau8b = 0.0, sb[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    const double wk = ck[k] * (t[k] - tbar) / S;
-    Cb -= nu * wk * dq[k] / S;
-    const double tb = ck[k] * nu * (dq[k] - fr) / S;  // c_k * dL/dalpha_k
-    tau8b += tb / s[k];
-    sb[k] = -tb * t[k] / s[k];
+    const double wk = ck[k] * (t[k] - tbar) * iS;
+    Cb -= nu * wk * dq[k] * iS;
+    const double tb = ck[k] * nu * (dq[k] - fr) * iS;  // c_k * dL/dalpha_k
+    tau8b += tb * is[k];
+    sb[k] = -tb * t[k] * is[k];
   }
   const double rb = Cb * 2.0 * A * r;
-  const double numb = rb / den;
-  const double denb = -rb * r / den;
+  const double numb = rb * iden;
+  const double denb = -rb * r * iden;
   double IS0b = sb[0] + numb, IS1b = sb[1], IS2b = sb[2] + numb;
   const double t5b = -numb + denb;
   const double sg = diff > 0.0 ? 1.0 : (diff < 0.0 ? -1.0 : 0.0);
@@ -113,12 +116,12 @@ __device__ __forceinline__ void wzn_grad(const double* v, double nu, double eps,
   const double A1b = (13.0 / 6.0) * A1 * IS1b, B1b = 0.5 * B1 * IS1b;
   const double A2b = (13.0 / 6.0) * A2 * IS2b, B2b = 0.5 * B2 * IS2b;
   const double qb0 = nu * om[0], qb1 = nu * om[1], qb2 = nu * om[2];
-  g[0] = d4b + A0b + B0b + qb0 / 3.0;
-  g[1] = -4.0 * d4b - 2.0 * A0b - 4.0 * B0b + A1b + B1b - qb0 * (7.0 / 6.0) - qb1 / 6.0;
+  g[0] = d4b + A0b + B0b + qb0 * (1.0 / 3.0);
+  g[1] = -4.0 * d4b - 2.0 * A0b - 4.0 * B0b + A1b + B1b - qb0 * (7.0 / 6.0) - qb1 * (1.0 / 6.0);
   g[2] = 6.0 * d4b + A0b + 3.0 * B0b - 2.0 * A1b + A2b + 3.0 * B2b + qb0 * (11.0 / 6.0) +
-         qb1 * (5.0 / 6.0) + qb2 / 3.0;
-  g[3] = -4.0 * d4b + A1b - B1b - 2.0 * A2b - 4.0 * B2b + qb1 / 3.0 + qb2 * (5.0 / 6.0);
-  g[4] = d4b + A2b + B2b - qb2 / 6.0;
+         qb1 * (5.0 / 6.0) + qb2 * (1.0 / 3.0);
+  g[3] = -4.0 * d4b + A1b - B1b - 2.0 * A2b - 4.0 * B2b + qb1 * (1.0 / 3.0) + qb2 * (5.0 / 6.0);
+  g[4] = d4b + A2b + B2b - qb2 * (1.0 / 6.0);
 }
 
 // Boundary index map: periodic wrap or transmissive clamp of any cell index p (the integer
@@ -132,19 +135,25 @@ __device__ __forceinline__ int64_t map_cell(int64_t p, int64_t n, int bc) {
   return p < 0 ? 0 : n - 1;
 }
 
-template <int NT>
-__global__ __launch_bounds__(NT) void vjp_kernel(VjpArgs a) {
-  constexpr int NW = NT + 10;  // staged split-flux cells: g0-5 .. g0+NT+4
-  constexpr int NM = NT + 6;   // staged cotangent cells:  g0-3 .. g0+NT+2
-  constexpr int NI = NT + 5;   // interfaces (right interface of cell e): e = g0-3 .. g0+NT+1
-  __shared__ double Wp[3][NW], Wm[3][NW], MU[3][NM], G[10][NI];
+// One workgroup of 256 threads per tile of TC = 64 output cells; every phase spreads its
+// (component, interface) or (component, cell) tasks over the threads.
+constexpr int VJP_TC = 64;
+constexpr int VJP_NT = 256;
+
+__global__ __launch_bounds__(VJP_NT) void vjp_kernel(VjpArgs a) {
+  constexpr int TC = VJP_TC;
+  constexpr int NW = TC + 10;  // staged split-flux cells: g0-5 .. g0+TC+4
+  constexpr int NM = TC + 6;   // staged cotangent cells:  g0-3 .. g0+TC+2
+  constexpr int NI = TC + 5;   // interfaces (right interface of cell e): e = g0-3 .. g0+TC+1
+  __shared__ double Wp[3][NW], Wm[3][NW], MU[3][NM], G[3][10][NI], WB[3][2][TC];
   const int tid = threadIdx.x;
   const int64_t n = a.n;
-  const int64_t g0 = (int64_t)blockIdx.x * NT;
+  const int64_t g0 = (int64_t)blockIdx.x * TC;
   const double alpha = a.alpha_arr ? a.alpha_arr[0] : a.alpha_const;
   const double gm1 = a.gamma - 1.0;
 
-  for (int i = tid; i < NW; i += NT) {
+  if (tid < NW) {
+    const int i = tid;
     const int64_t cell = map_cell(g0 - 5 + i, n, a.bc);
     const double rho = a.U[cell], m = a.U[n + cell], E = a.U[2 * n + cell];
     const double u = m / rho;
@@ -156,8 +165,8 @@ __global__ __launch_bounds__(NT) void vjp_kernel(VjpArgs a) {
       Wp[c][i] = 0.5 * (F[c] + alpha * Uc[c]);
       Wm[c][i] = 0.5 * (F[c] - alpha * Uc[c]);
     }
-  }
-  for (int i = tid; i < NM; i += NT) {
+  } else if (tid >= 128 && tid < 128 + NM) {
+    const int i = tid - 128;
     const int64_t cell = g0 - 3 + i;
     int64_t src = -1;
     if (a.bc == 0) src = map_cell(cell, n, 0);
@@ -167,56 +176,67 @@ __global__ __launch_bounds__(NT) void vjp_kernel(VjpArgs a) {
   }
   __syncthreads();
 
-  const int64_t j = g0 + tid;  // this thread's output cell
-  double wbp[3] = {0.0, 0.0, 0.0}, wbm[3] = {0.0, 0.0, 0.0};
-  for (int c = 0; c < 3; ++c) {
-    for (int i = tid; i < NI; i += NT) {
-      const int64_t e = g0 - 3 + i;
-      const bool valid = a.bc == 0 || (e >= -1 && e <= n - 1);
-      const double nu = valid ? (MU[c][i + 1] - MU[c][i]) / a.dx : 0.0;
-      double v[5], gp[5], gmv[5];
+  // (component, interface) tasks: nu_e times the partials of the two reconstructions
+  if (tid < 3 * NI) {
+    const int c = tid / NI, i = tid - c * NI;
+    const int64_t e = g0 - 3 + i;
+    const bool valid = a.bc == 0 || (e >= -1 && e <= n - 1);
+    const double nu = valid ? (MU[c][i + 1] - MU[c][i]) * (1.0 / a.dx) : 0.0;
+    double v[5], gp[5], gmv[5];
 #pragma unroll
-      for (int k = 0; k < 5; ++k) v[k] = Wp[c][i + k];          // cells e-2 .. e+2
-      wzn_grad(v, nu, a.eps, a.A, gp);
+    for (int k = 0; k < 5; ++k) v[k] = Wp[c][i + k];  // cells e-2 .. e+2
+    wzn_grad(v, nu, a.eps, a.A, gp);
 #pragma unroll
-      for (int k = 0; k < 5; ++k) v[k] = Wm[c][i + 5 - k];      // cells e+3 .. e-1
-      wzn_grad(v, nu, a.eps, a.A, gmv);
+    for (int k = 0; k < 5; ++k) v[k] = Wm[c][i + 5 - k];  // cells e+3 .. e-1
+    wzn_grad(v, nu, a.eps, a.A, gmv);
 #pragma unroll
-      for (int k = 0; k < 5; ++k) {
-        G[k][i] = gp[k];
-        G[5 + k][i] = gmv[k];
-      }
+    for (int k = 0; k < 5; ++k) {
+      G[c][k][i] = gp[k];
+      G[c][5 + k][i] = gmv[k];
     }
-    __syncthreads();
+  }
+  __syncthreads();
+
+  // (component, cell) tasks: gather the partials of the interfaces whose stencils hold the cell
+  if (tid < 3 * TC) {
+    const int c = tid / TC, t = tid - c * TC;
+    const int64_t j = g0 + t;
+    double sp = 0.0, sm = 0.0;
     if (j < n) {
-      double sp = 0.0, sm = 0.0;
-      const int base = (int)(j - (g0 - 3));  // interface slot of e = j
+      const int base = t + 3;  // interface slot of e = j
       if (j >= 5 && j + 5 < n) {
-        // interior: cell j is slot k = j - e + 2 of the f^+ stencil of interface e and slot
-        // k = e + 3 - j of the f^- stencil
+        // interior: cell j is slot 2 - de of the f^+ stencil and slot 3 + de of the f^-
+        // stencil of interface e = j + de
 #pragma unroll
         for (int de = -3; de <= 2; ++de) {
-          if (de >= -2) sp += G[2 - de][base + de];
-          if (de <= 1) sm += G[5 + 3 + de][base + de];
+          if (de >= -2) sp += G[c][2 - de][base + de];
+          if (de <= 1) sm += G[c][5 + 3 + de][base + de];
         }
       } else {
-#pragma unroll
         for (int de = -3; de <= 2; ++de) {
           const int64_t e = j + de;
 #pragma unroll
           for (int k = 0; k < 5; ++k) {
-            if (map_cell(e - 2 + k, n, a.bc) == j) sp += G[k][base + de];
-            if (map_cell(e + 3 - k, n, a.bc) == j) sm += G[5 + k][base + de];
+            if (map_cell(e - 2 + k, n, a.bc) == j) sp += G[c][k][base + de];
+            if (map_cell(e + 3 - k, n, a.bc) == j) sm += G[c][5 + k][base + de];
           }
         }
       }
-      wbp[c] = sp;
-      wbm[c] = sm;
     }
-    __syncthreads();
+    WB[c][0][t] = sp;
+    WB[c][1][t] = sm;
   }
-  if (j >= n) return;
+  __syncthreads();
 
+  if (tid >= TC) return;
+  const int64_t j = g0 + tid;
+  if (j >= n) return;
+  double wbp[3], wbm[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    wbp[c] = WB[c][0][tid];
+    wbm[c] = WB[c][1][tid];
+  }
   // f^{+-}_c = (F_c +- alpha U_c)/2:  Ubar_d = 1/2 sum_c (wbp_c + wbm_c) dF_c/dU_d
   //                                          + alpha/2 (wbp_d - wbm_d)
   const double rho = a.U[j], m = a.U[n + j], E = a.U[2 * n + j];
@@ -253,10 +273,9 @@ __global__ __launch_bounds__(NT) void vjp_kernel(VjpArgs a) {
 }
 
 static int launch_vjp(const VjpArgs& a, hipStream_t s) {
-  constexpr int NT = 256;
-  const int64_t blocks = (a.n + NT - 1) / NT;
+  const int64_t blocks = (a.n + VJP_TC - 1) / VJP_TC;
   if (blocks > 0x7fffffff) return set_error(WZN_ERR_SIZE, "grid too large (vjp)");
-  hipLaunchKernelGGL((vjp_kernel<NT>), dim3((unsigned)blocks), dim3(NT), 0, s, a);
+  hipLaunchKernelGGL(vjp_kernel, dim3((unsigned)blocks), dim3(VJP_NT), 0, s, a);
   return check_launch("vjp_kernel");
 }
 
