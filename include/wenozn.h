@@ -81,6 +81,12 @@ const char* wzn_status_string(int32_t status);
 /* Message of the last failing call on this host thread ("" if none). */
 const char* wzn_last_error(void);
 
+/* Process-wide launch shape of the 1D Euler row kernel (threads per workgroup nt, consecutive
+ * interfaces per thread k): supported (256,1), (256,2), (256,4), (128,4), (128,8), (64,1),
+ * (64,2), (64,4), (64,8); (0,0) restores the automatic choice from the grid size.  Set by the
+ * autotuner; results do not depend on it (bit for bit). */
+int32_t wzn_set_row_tuning(int32_t nt, int32_t k);
+
 /* Bytes of device workspace `ws` needed by any entry point for grids up to nx * ny cells
  * (ny = 1 in 1D).  Currently a small constant. */
 size_t wzn_workspace_bytes(const wzn_params* p, int64_t nx, int64_t ny);

@@ -76,3 +76,43 @@ def tune_batched(u, offsets, dx, order=None, probe_steps=3, candidates=CANDIDATE
         db[key] = {"choice": [nt, k, bpc], "ms": timings}
         _store(db)
     return api.batch_tuning(nt, k, bpc), timings
+
+
+ROW_SHAPES = [(256, 4), (256, 2), (256, 1), (128, 4), (128, 8), (64, 8), (64, 4), (64, 2),
+              (64, 1)]
+
+
+def set_row_tuning(nt, k):
+    from ._lib import check, lib
+    check(lib().wzn_set_row_tuning(int(nt), int(k)))
+
+
+def tune_rows(n, steps=50, shapes=ROW_SHAPES, log=None, apply=True):
+    """Time the 1D Euler TVD-RK3 stage kernel at grid size n for every launch shape on
+    Shu-Osher-like data and (optionally) install the fastest process-wide.  Returns
+    ((nt, k), {shape: ms per step})."""
+    from . import inputs as I
+    u0, dx = I.shu_osher_like(n)
+    base = torch.tensor(u0, dtype=torch.float64, device="cuda")
+    u = base.clone()
+    stage = torch.empty((2,) + tuple(u.shape), dtype=torch.float64, device="cuda")
+    prm = api.params("euler")
+    timings = {}
+    for nt, k in shapes:
+        set_row_tuning(nt, k)
+        u.copy_(base)
+        api.rk3_run_1d(u, dx, 2, prm=prm, stage=stage)
+        u.copy_(base)
+        torch.cuda.synchronize()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        api.rk3_run_1d(u, dx, steps, prm=prm, stage=stage)
+        e.record()
+        torch.cuda.synchronize()
+        timings["%d/%d" % (nt, k)] = s.elapsed_time(e) / steps
+        if log:
+            log("rows n=%d nt=%d k=%d: %.4f ms/step" % (n, nt, k, timings["%d/%d" % (nt, k)]))
+    best = min(timings, key=timings.get)
+    nt, k = (int(x) for x in best.split("/"))
+    set_row_tuning(nt, k) if apply else set_row_tuning(0, 0)
+    return (nt, k), timings

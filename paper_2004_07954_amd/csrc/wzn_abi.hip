@@ -34,22 +34,17 @@ int launch_fill_double(double* p, double v, hipStream_t s) {
   return check_launch("fill_double_kernel");
 }
 
-// Launch shape of the 1D row kernel: the widest tile (most sliding-window reuse) that still
-// gives >= 2048 waves (8 per CU); small grids fall back to the shape with the most waves.
+static Tuning1D g_row_override = {0, 0};
+
+// Launch shape of the 1D row kernel: the caller's override if set; otherwise 256-thread
+// workgroups (measured fastest at every size on MI355X) with the widest tile that still
+// leaves >= 256 workgroups (one per CU): k = 4 from 2^18 cells, k = 2 from 2^15, else 1.
 Tuning1D tuning_1d(int nv, int64_t n) {
   if (nv == 1) return Tuning1D{64, 4};
-  static const Tuning1D shapes[] = {{256, 4}, {128, 4}, {64, 4}, {64, 2}, {64, 1}};
-  Tuning1D best = shapes[0];
-  int64_t best_waves = 0;
-  for (const Tuning1D& t : shapes) {
-    const int64_t waves = (n + t.nt * t.k - 1) / (t.nt * t.k) * (t.nt / 64);
-    if (waves >= 2048) return t;
-    if (waves > best_waves) {
-      best_waves = waves;
-      best = t;
-    }
-  }
-  return best;
+  if (g_row_override.nt > 0) return g_row_override;
+  if (n >= (int64_t)256 * 4 * 256) return Tuning1D{256, 4};
+  if (n >= (int64_t)256 * 2 * 64) return Tuning1D{256, 2};
+  return Tuning1D{256, 1};
 }
 
 static int check_params(const wzn_params* p, bool allow_fp32) {
@@ -141,6 +136,19 @@ const char* wzn_status_string(int32_t status) {
 }
 
 const char* wzn_last_error(void) { return g_err; }
+
+int32_t wzn_set_row_tuning(int32_t nt, int32_t k) {
+  g_err[0] = 0;
+  if (nt == 0 && k == 0) {
+    g_row_override = Tuning1D{0, 0};
+    return WZN_OK;
+  }
+  const bool ok = (nt == 256 && (k == 1 || k == 2 || k == 4)) || (nt == 128 && (k == 4 || k == 8)) ||
+                  (nt == 64 && (k == 1 || k == 2 || k == 4 || k == 8));
+  if (!ok) return set_error(WZN_ERR_ARG, "unsupported row tuning (nt=%d, k=%d)", nt, k);
+  g_row_override = Tuning1D{nt, k};
+  return WZN_OK;
+}
 
 size_t wzn_workspace_bytes(const wzn_params* p, int64_t nx, int64_t ny) {
   (void)p; (void)nx; (void)ny;

@@ -175,8 +175,13 @@ __device__ __forceinline__ int64_t bc_index(int64_t g, int64_t n, int bc) {
 }
 
 // Max of non-negative doubles through their bit patterns (order preserving; a NaN wins).
+// The slot only grows, so a plain read that already holds >= v makes the atomic unnecessary;
+// a stale read only costs an atomic that was not needed.  This keeps the number of atomics on
+// the one address far below the number of workgroups.
 __device__ __forceinline__ void atomic_max_pos(unsigned long long* slot, double v) {
-  atomicMax(slot, (unsigned long long)__double_as_longlong(v));
+  const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
+  const unsigned long long seen = __atomic_load_n(slot, __ATOMIC_RELAXED);
+  if (bits > seen) atomicMax(slot, bits);
 }
 
 __device__ __forceinline__ double slot_value(const unsigned long long* slot) {
