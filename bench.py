@@ -216,6 +216,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--steps-batched", type=int, default=500)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed region, copy 256 MiB with a plain torch copy "
+                         "(reference kernel for rocprof FETCH_SIZE / WRITE_SIZE scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -297,6 +300,12 @@ def main():
                      "kernel_ms": kernel_ms},
         "cpu_baseline": None,
     }
+    if args.copy_calibration:
+        a = torch.ones(32 << 20, dtype=torch.float64, device=dev)  # 256 MiB
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        rec["copy_calibration_bytes"] = a.numel() * 8
     if not args.no_2d:
         log("2D fp64 and fp32, 4096^2")
         rec["secondary"] = {"euler2d_f64": bench_2d(args.steps_2d, "f64"),

@@ -238,3 +238,16 @@ def test_2d_time_step(orc):
     c = np.sqrt(1.4 * p / rho)
     dtx, dty = dx / np.max(np.abs(u) + c), dy / np.max(np.abs(v) + c)
     assert dts[0] == pytest.approx(0.5 * dtx * dty / (dtx + dty), rel=1e-14)
+
+
+@pytest.mark.slow
+def test_batched_instance_1767_loses_positivity_in_the_oracle(orc):
+    """Instance 1767 of the seed-4 shock-tube batch is a case where component-wise LF
+    WENO-ZN (no positivity limiter) drives rho below zero: the oracle alone reaches rho < 0
+    within 250 steps (CFL 0.5), so the GPU batch is right to show it too."""
+    U, offs, dx = I.shock_tube_batch(4096, seed=4)
+    b = 1767
+    u = U[:, offs[b]:offs[b + 1]].copy()
+    u, _, _ = orc.rk3_run_1d(u, dx[b], 250, cfl=0.5)
+    with np.errstate(invalid="ignore"):
+        assert not (np.isfinite(u).all() and u[0].min() > 0)
