@@ -78,19 +78,23 @@ def tune_batched(u, offsets, dx, order=None, probe_steps=3, candidates=CANDIDATE
     return api.batch_tuning(nt, k, bpc), timings
 
 
-ROW_SHAPES = [(256, 4), (256, 2), (256, 1), (128, 4), (128, 8), (64, 8), (64, 4), (64, 2),
-              (64, 1)]
+# (threads per workgroup, cells per thread, layout): layout 0 stages a workgroup tile in LDS,
+# layout 1 gives every wave its own run of 64 k cells (no LDS staging), layout 2 stages the
+# two signs of the split flux one after the other (half the LDS of layout 0).
+ROW_SHAPES = [(256, 4, 0), (256, 2, 0), (256, 1, 0), (128, 4, 0), (128, 8, 0), (64, 8, 0),
+              (64, 4, 0), (64, 2, 0), (64, 1, 0), (256, 4, 1), (256, 2, 1), (64, 4, 1),
+              (64, 2, 1), (256, 4, 2), (256, 2, 2), (128, 4, 2), (64, 4, 2)]
 
 
-def set_row_tuning(nt, k):
+def set_row_tuning(nt, k, layout=0):
     from ._lib import check, lib
-    check(lib().wzn_set_row_tuning(int(nt), int(k)))
+    check(lib().wzn_set_row_tuning(int(nt), int(k), int(layout)))
 
 
 def tune_rows(n, steps=50, shapes=ROW_SHAPES, log=None, apply=True):
     """Time the 1D Euler TVD-RK3 stage kernel at grid size n for every launch shape on
     Shu-Osher-like data and (optionally) install the fastest process-wide.  Returns
-    ((nt, k), {shape: ms per step})."""
+    ((nt, k, layout), {shape: ms per step})."""
     from . import inputs as I
     u0, dx = I.shu_osher_like(n)
     base = torch.tensor(u0, dtype=torch.float64, device="cuda")
@@ -98,8 +102,8 @@ def tune_rows(n, steps=50, shapes=ROW_SHAPES, log=None, apply=True):
     stage = torch.empty((2,) + tuple(u.shape), dtype=torch.float64, device="cuda")
     prm = api.params("euler")
     timings = {}
-    for nt, k in shapes:
-        set_row_tuning(nt, k)
+    for nt, k, lay in shapes:
+        set_row_tuning(nt, k, lay)
         u.copy_(base)
         api.rk3_run_1d(u, dx, 2, prm=prm, stage=stage)
         u.copy_(base)
@@ -109,10 +113,11 @@ def tune_rows(n, steps=50, shapes=ROW_SHAPES, log=None, apply=True):
         api.rk3_run_1d(u, dx, steps, prm=prm, stage=stage)
         e.record()
         torch.cuda.synchronize()
-        timings["%d/%d" % (nt, k)] = s.elapsed_time(e) / steps
+        key = "%d/%d/%d" % (nt, k, lay)
+        timings[key] = s.elapsed_time(e) / steps
         if log:
-            log("rows n=%d nt=%d k=%d: %.4f ms/step" % (n, nt, k, timings["%d/%d" % (nt, k)]))
+            log("rows n=%d nt=%d k=%d layout=%d: %.4f ms/step" % (n, nt, k, lay, timings[key]))
     best = min(timings, key=timings.get)
-    nt, k = (int(x) for x in best.split("/"))
-    set_row_tuning(nt, k) if apply else set_row_tuning(0, 0)
-    return (nt, k), timings
+    nt, k, lay = (int(x) for x in best.split("/"))
+    set_row_tuning(nt, k, lay) if apply else set_row_tuning(0, 0)
+    return (nt, k, lay), timings

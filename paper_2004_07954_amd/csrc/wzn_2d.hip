@@ -95,7 +95,7 @@ void col_kernel(ColArgs<T> a) {
   }
 
   const T gm1 = T(a.gamma) - T(1);
-  const T eps_s = T(a.eps_s), A = T(a.A);
+  const T eps_s = T(a.eps_s), A = window_const<T>(a.A);
   const T coef = T(-0.5 / a.dy);
   const double gamma = a.gamma;
   double sxm = 0.0, sym = 0.0;
@@ -115,9 +115,10 @@ void col_kernel(ColArgs<T> a) {
         q.mx = a.uin[a.plane + gi];
         q.my = a.uin[2 * a.plane + gi];
         q.E = a.uin[3 * a.plane + gi];
-        const T u = q.mx / q.rho;
-        q.v = q.my / q.rho;
-        q.p = gm1 * (q.E - (T(0.5) * q.rho) * (u * u + q.v * q.v));
+        const T r = rcp_nr(q.rho);
+        const T u = q.mx * r;
+        q.v = q.my * r;
+        q.p = gm1 * fma_t(-(T(0.5) * q.my), q.v, fma_t(-(T(0.5) * q.mx), u, q.E));
         P[i] = q;
       }
       // per component: reconstruct the KY top interfaces, then finish the KY rows
@@ -250,7 +251,7 @@ static ColArgs<T> col_args(const wzn_params* p, int64_t nx, int64_t ny, double d
   return a;
 }
 
-static Tuning1D tuning_2dx() { return Tuning1D{256, 4}; }
+static Tuning1D tuning_2dx() { return Tuning1D{256, 4, ROW_LDS_TILE}; }
 
 template <typename T>
 int rhs_2d_t(const wzn_params* p, const T* u, T* dudt, int64_t nx, int64_t ny, double dx,

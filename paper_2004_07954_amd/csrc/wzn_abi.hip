@@ -34,17 +34,20 @@ int launch_fill_double(double* p, double v, hipStream_t s) {
   return check_launch("fill_double_kernel");
 }
 
-static Tuning1D g_row_override = {0, 0};
+static Tuning1D g_row_override = {0, 0, 0};
 
 // Launch shape of the 1D row kernel: the caller's override if set; otherwise 256-thread
 // workgroups (measured fastest at every size on MI355X) with the widest tile that still
 // leaves >= 256 workgroups (one per CU): k = 4 from 2^18 cells, k = 2 from 2^15, else 1.
 Tuning1D tuning_1d(int nv, int64_t n) {
-  if (nv == 1) return Tuning1D{64, 4};
+  if (nv == 1)
+    return g_row_override.nt > 0 && g_row_override.layout == ROW_WAVE_RUNS
+               ? Tuning1D{256, 4, ROW_WAVE_RUNS}
+               : Tuning1D{64, 4, ROW_LDS_TILE};
   if (g_row_override.nt > 0) return g_row_override;
-  if (n >= (int64_t)256 * 4 * 256) return Tuning1D{256, 4};
-  if (n >= (int64_t)256 * 2 * 64) return Tuning1D{256, 2};
-  return Tuning1D{256, 1};
+  if (n >= (int64_t)256 * 4 * 256) return Tuning1D{256, 4, ROW_LDS_TILE};
+  if (n >= (int64_t)256 * 2 * 64) return Tuning1D{256, 2, ROW_LDS_TILE};
+  return Tuning1D{256, 1, ROW_LDS_TILE};
 }
 
 static int check_params(const wzn_params* p, bool allow_fp32) {
@@ -137,16 +140,26 @@ const char* wzn_status_string(int32_t status) {
 
 const char* wzn_last_error(void) { return g_err; }
 
-int32_t wzn_set_row_tuning(int32_t nt, int32_t k) {
+int32_t wzn_set_row_tuning(int32_t nt, int32_t k, int32_t layout) {
   g_err[0] = 0;
   if (nt == 0 && k == 0) {
-    g_row_override = Tuning1D{0, 0};
+    g_row_override = Tuning1D{0, 0, 0};
     return WZN_OK;
   }
-  const bool ok = (nt == 256 && (k == 1 || k == 2 || k == 4)) || (nt == 128 && (k == 4 || k == 8)) ||
-                  (nt == 64 && (k == 1 || k == 2 || k == 4 || k == 8));
-  if (!ok) return set_error(WZN_ERR_ARG, "unsupported row tuning (nt=%d, k=%d)", nt, k);
-  g_row_override = Tuning1D{nt, k};
+  bool ok;
+  if (layout == ROW_LDS_TILE)
+    ok = (nt == 256 && (k == 1 || k == 2 || k == 4)) || (nt == 128 && (k == 4 || k == 8)) ||
+         (nt == 64 && (k == 1 || k == 2 || k == 4 || k == 8));
+  else if (layout == ROW_WAVE_RUNS)
+    ok = (nt == 256 || nt == 64) && (k == 2 || k == 4);
+  else if (layout == ROW_LDS_SPLIT)
+    ok = (nt == 256 && (k == 2 || k == 4)) || ((nt == 128 || nt == 64) && k == 4);
+  else
+    ok = false;
+  if (!ok)
+    return set_error(WZN_ERR_ARG, "unsupported row tuning (nt=%d, k=%d, layout=%d)", nt, k,
+                     layout);
+  g_row_override = Tuning1D{nt, k, layout};
   return WZN_OK;
 }
 

@@ -25,7 +25,10 @@
 // and, since sum_k omega_k = 1,
 //   fhat = q1 + (c0 B0 (q0 - q1) + c2 B2 (q2 - q1)) / sum_k c_k B_k
 // with q0 - q1 = (D_m - D_{m+1})/3, q2 - q1 = (D_{m+1} - D_{m+2})/6 and
-// q1 = (v_{m+2} + v_{m+3})/2 - D_{m+1}/6 (eq:4 rewritten with differences).
+// q1 = (v_{m+2} + v_{m+3})/2 - D_{m+1}/6 (eq:4 rewritten with differences).  Numerator and
+// denominator are both taken times 10 / c0 (so the linear weights become 1, 6, 3) and every
+// B_k times 1/4 (A/4 multiplies num^2 and the fourth difference is not doubled): common
+// factors of numerator and denominator that change no weight.
 // Every term is >= eps^5 ~ 1e-200 for eps = 1e-40 (fp64 safe) and < 1e300 for
 // |w| < ~1e30.
 #pragma once
@@ -49,12 +52,55 @@ __device__ __forceinline__ double fast_div(double num, double den) {
   return __builtin_fma(res, r, q);
 }
 
+// 1/x with one v_rcp and Newton steps (about 1 ulp for normal x).
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(e, r, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(e, r, r);
+}
+__device__ __forceinline__ float rcp_nr(float x) {
+  const float r = __builtin_amdgcn_rcpf(x);
+  const float e = __builtin_fmaf(-x, r, 1.0f);
+  return __builtin_fmaf(e, r, r);
+}
+
+// num / den from one v_rcp (relative error up to ~5e-8) and one correction: with r = rcp(den)
+// and e = 1 - den r, num r (1 + e) has relative error ~e^2 (~2e-15).  Used for the nonlinear
+// correction term of the reconstruction, whose error is relative to itself.
+__device__ __forceinline__ double approx_div(double num, double den) {
+  const double r = __builtin_amdgcn_rcp(den);
+  const double e = __builtin_fma(-den, r, 1.0);
+  const double q = num * r;
+  return __builtin_fma(q, e, q);
+}
+
+// sqrt(x) for x >= 0 from one v_rsq (relative error up to ~5e-8) and one Goldschmidt step:
+// with y = rsq(x), s = x y, h = y / 2, s (1 + (1/2 - s h)) has relative error ~1.5 (s h)^2
+// deviations (~4e-15).  x = 0 gives 0; x < 0 or NaN gives NaN, as sqrt does.
+__device__ __forceinline__ double sqrt_gs(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  const double s = x * y;
+  const double h = 0.5 * y;
+  const double r = __builtin_fma(-s, h, 0.5);
+  const double t = __builtin_fma(s, r, s);
+  return x == 0.0 ? 0.0 : t;
+}
+
 // K consecutive WENO-ZN interface values from a window v[0 .. K+3].
 // Interface m uses stencil v[m .. m+4] and returns fhat_{m} (the value at the interface
 // between v[m+2] and v[m+3]).
+// The constant A of eq:function in the form wzn_window<K> takes it: A / 4 for the fp64 window
+// (see the normalisation above), A itself for the fp32 window.
+template <typename T> __device__ __forceinline__ T window_const(double A);
+template <> __device__ __forceinline__ double window_const<double>(double A) { return 0.25 * A; }
+template <> __device__ __forceinline__ float window_const<float>(double A) { return float(A); }
+
+// Aq = window_const<double>(A) = A / 4.
 template <int K>
 __device__ __forceinline__ void wzn_window(const double* v, double* fh, double eps_s,
-                                           double A) {
+                                           double Aq) {
   constexpr int NG = K + 3;
   constexpr int ND = K + 2;
   double g[NG];
@@ -82,23 +128,24 @@ __device__ __forceinline__ void wzn_window(const double* v, double* fh, double e
     const double num = ((IS0 + IS2) - t5) + eps_s;
     const double den = t5 + eps_s;
     const double s0 = IS0 + eps_s, s1 = IS1 + eps_s, s2 = IS2 + eps_s;
-    // 4 tau8 = (2 (D_m - 2 D_{m+1} + D_{m+2}))^2 ; H = 4 tau8 den^2
+    // tau8 (in the units of the scaled indicators) = (2 b)^2, b = D_m - 2 D_{m+1} + D_{m+2};
+    // H = tau8 den^2 / 4, G = A num^2 / 4
     const double b = __builtin_fma(-2.0, D[m + 1], D[m] + D[m + 2]);
-    const double bd = (b + b) * den;
+    const double bd = b * den;
     const double H = bd * bd;
-    const double G = (A * num) * num;
+    const double G = (Aq * num) * num;
     const double t0 = __builtin_fma(G, s0, H);
     const double t1 = __builtin_fma(G, s1, H);
     const double t2 = __builtin_fma(G, s2, H);
     const double B0 = (s1 * s2) * t0;
     const double B1 = (s0 * s2) * t1;
     const double B2 = (s0 * s1) * t2;
-    const double S = __builtin_fma(0.1, B0, __builtin_fma(0.6, B1, 0.3 * B2));
-    const double x0 = (D[m] - D[m + 1]) * (0.1 / 3.0);
-    const double x2 = (D[m + 1] - D[m + 2]) * (0.3 / 6.0);
+    const double S = __builtin_fma(6.0, B1, __builtin_fma(3.0, B2, B0));
+    const double x0 = (D[m] - D[m + 1]) * (1.0 / 3.0);
+    const double x2 = (D[m + 1] - D[m + 2]) * 0.5;
     const double nr = __builtin_fma(B0, x0, B2 * x2);
     const double base = __builtin_fma(-1.0 / 6.0, D[m + 1], 0.5 * (v[m + 2] + v[m + 3]));
-    fh[m] = base + fast_div(nr, S);
+    fh[m] = base + approx_div(nr, S);
   }
 }
 

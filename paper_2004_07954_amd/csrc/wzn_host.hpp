@@ -31,9 +31,13 @@ inline Workspace make_workspace(void* ws) {
 }
 
 struct Tuning1D {
-  int nt;  // threads per workgroup
-  int k;   // consecutive interfaces per thread
+  int nt;      // threads per workgroup
+  int k;       // consecutive cells (interfaces) per thread
+  int layout;  // ROW_LDS_TILE: workgroup tile staged in LDS (both signs of the split flux at
+               // once); ROW_WAVE_RUNS: one run per wave; ROW_LDS_SPLIT: LDS tile, one sign of
+               // the split flux at a time
 };
+enum { ROW_LDS_TILE = 0, ROW_WAVE_RUNS = 1, ROW_LDS_SPLIT = 2 };
 Tuning1D tuning_1d(int nv, int64_t n);
 
 int set_error(int code, const char* fmt, ...);
