@@ -83,15 +83,14 @@ const char* wzn_last_error(void);
 
 /* Process-wide launch shape of the 1D Euler row kernel: threads per workgroup nt, consecutive
  * cells per thread k, and the layout:
- *   WZN_ROW_LDS_TILE  (0) one tile of nt*k cells per workgroup, staged in LDS: (256,1),
- *                     (256,2), (256,4), (128,4), (128,8), (64,1), (64,2), (64,4), (64,8);
- *   WZN_ROW_WAVE_RUNS (1) one run of 64*k cells per 64-lane wave, neighbours exchanged by
- *                     cross-lane permutes, no LDS staging: nt in {64, 256}, k in {2, 4};
- *   WZN_ROW_LDS_SPLIT (2) the LDS tile with the two signs of the split flux staged one after
- *                     the other (half the LDS): (256,2), (256,4), (128,4), (64,4).
+ *   WZN_ROW_LDS_TILE  (0) one tile of nt*k cells per workgroup, both signs of the split flux
+ *                     staged in LDS: (256,1), (256,2), (256,4), (128,4), (128,8), (64,1),
+ *                     (64,2), (64,4), (64,8);
+ *   WZN_ROW_LDS_SPLIT (1) the same tile with the two signs staged one after the other (half
+ *                     the LDS): (256,2), (256,4), (128,4), (64,4).
  * (0, 0, any) restores the automatic choice from the grid size.  Set by the autotuner; results
  * do not depend on it (bit for bit).  Returns WZN_ERR_ARG for an unsupported shape. */
-enum { WZN_ROW_LDS_TILE = 0, WZN_ROW_WAVE_RUNS = 1, WZN_ROW_LDS_SPLIT = 2 };
+enum { WZN_ROW_LDS_TILE = 0, WZN_ROW_LDS_SPLIT = 1 };
 int32_t wzn_set_row_tuning(int32_t nt, int32_t k, int32_t layout);
 
 /* Bytes of device workspace `ws` needed by any entry point for grids up to nx * ny cells

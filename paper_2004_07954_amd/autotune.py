@@ -78,12 +78,10 @@ def tune_batched(u, offsets, dx, order=None, probe_steps=3, candidates=CANDIDATE
     return api.batch_tuning(nt, k, bpc), timings
 
 
-# (threads per workgroup, cells per thread, layout): layout 0 stages a workgroup tile in LDS,
-# layout 1 gives every wave its own run of 64 k cells (no LDS staging), layout 2 stages the
-# two signs of the split flux one after the other (half the LDS of layout 0).
+# (threads per workgroup, cells per thread, layout): layout 0 stages both signs of the split
+# flux of a workgroup tile in LDS, layout 1 stages one sign at a time (half the LDS).
 ROW_SHAPES = [(256, 4, 0), (256, 2, 0), (256, 1, 0), (128, 4, 0), (128, 8, 0), (64, 8, 0),
-              (64, 4, 0), (64, 2, 0), (64, 1, 0), (256, 4, 1), (256, 2, 1), (64, 4, 1),
-              (64, 2, 1), (256, 4, 2), (256, 2, 2), (128, 4, 2), (64, 4, 2)]
+              (64, 4, 0), (64, 2, 0), (64, 1, 0), (256, 4, 1), (256, 2, 1), (128, 4, 1), (64, 4, 1)]
 
 
 def set_row_tuning(nt, k, layout=0):

@@ -40,10 +40,7 @@ static Tuning1D g_row_override = {0, 0, 0};
 // workgroups (measured fastest at every size on MI355X) with the widest tile that still
 // leaves >= 256 workgroups (one per CU): k = 4 from 2^18 cells, k = 2 from 2^15, else 1.
 Tuning1D tuning_1d(int nv, int64_t n) {
-  if (nv == 1)
-    return g_row_override.nt > 0 && g_row_override.layout == ROW_WAVE_RUNS
-               ? Tuning1D{256, 4, ROW_WAVE_RUNS}
-               : Tuning1D{64, 4, ROW_LDS_TILE};
+  if (nv == 1) return Tuning1D{64, 4, ROW_LDS_TILE};
   if (g_row_override.nt > 0) return g_row_override;
   if (n >= (int64_t)256 * 4 * 256) return Tuning1D{256, 4, ROW_LDS_TILE};
   if (n >= (int64_t)256 * 2 * 64) return Tuning1D{256, 2, ROW_LDS_TILE};
@@ -150,8 +147,6 @@ int32_t wzn_set_row_tuning(int32_t nt, int32_t k, int32_t layout) {
   if (layout == ROW_LDS_TILE)
     ok = (nt == 256 && (k == 1 || k == 2 || k == 4)) || (nt == 128 && (k == 4 || k == 8)) ||
          (nt == 64 && (k == 1 || k == 2 || k == 4 || k == 8));
-  else if (layout == ROW_WAVE_RUNS)
-    ok = (nt == 256 || nt == 64) && (k == 2 || k == 4);
   else if (layout == ROW_LDS_SPLIT)
     ok = (nt == 256 && (k == 2 || k == 4)) || ((nt == 128 || nt == 64) && k == 4);
   else

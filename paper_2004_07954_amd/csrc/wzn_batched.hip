@@ -38,7 +38,7 @@ __global__ __launch_bounds__(NT) void batched_kernel(BatchArgs b) {
   constexpr int TT = NT * K;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   double* W = reinterpret_cast<double*>(lds_raw);
-  __shared__ double EX[6];
+  __shared__ double EX[tile_ex_elems<SYS_EULER1, NT>()];
   __shared__ double red[NT / 64];
   __shared__ int next;
   const int tid = threadIdx.x;

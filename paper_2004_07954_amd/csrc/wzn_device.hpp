@@ -97,7 +97,11 @@ template <typename T> __device__ __forceinline__ T window_const(double A);
 template <> __device__ __forceinline__ double window_const<double>(double A) { return 0.25 * A; }
 template <> __device__ __forceinline__ float window_const<float>(double A) { return float(A); }
 
-// Aq = window_const<double>(A) = A / 4.
+// Aq = window_const<double>(A) = A / 4.  Per window element j the shared quantities are the
+// differences g_j, D_j, e_j = D_j - D_{j+1} and 13/3 D_j^2 + eps (so that each s_k = IS_k + eps
+// is one fma); per interface: tau5 = |s0 - s2|, num = (s0 + s2 - tau5) - eps (= IS0 + IS2 - tau5
+// + eps up to rounding, and only num^2 enters C), b = e_m - e_{m+1}, q1 = v_{m+2} + g_{m+2}/2
+// - D_{m+1}/6, q0 - q1 = e_m/3, q2 - q1 = e_{m+1}/6.
 template <int K>
 __device__ __forceinline__ void wzn_window(const double* v, double* fh, double eps_s,
                                            double Aq) {
@@ -109,28 +113,30 @@ __device__ __forceinline__ void wzn_window(const double* v, double* fh, double e
   double D[ND];
 #pragma unroll
   for (int j = 0; j < ND; ++j) D[j] = g[j + 1] - g[j];
-  // per-centre 13/3 D^2 (indicators scaled by 4)
+  // per-centre 13/3 D^2 + eps (indicators scaled by 4)
   double DD[ND];
 #pragma unroll
-  for (int j = 0; j < ND; ++j) DD[j] = (D[j] * (13.0 / 3.0)) * D[j];
+  for (int j = 0; j < ND; ++j) DD[j] = __builtin_fma(D[j] * (13.0 / 3.0), D[j], eps_s);
+  double e[K + 1];
+#pragma unroll
+  for (int j = 0; j <= K; ++j) e[j] = D[j] - D[j + 1];
 
 #pragma unroll
   for (int m = 0; m < K; ++m) {
     const double E0 = __builtin_fma(3.0, g[m + 1], -g[m]);
     const double E1 = g[m + 1] + g[m + 2];
     const double E2 = __builtin_fma(-3.0, g[m + 2], g[m + 3]);
-    const double IS0 = __builtin_fma(E0, E0, DD[m]);
-    const double IS1 = __builtin_fma(E1, E1, DD[m + 1]);
-    const double IS2 = __builtin_fma(E2, E2, DD[m + 2]);
+    const double s0 = __builtin_fma(E0, E0, DD[m]);
+    const double s1 = __builtin_fma(E1, E1, DD[m + 1]);
+    const double s2 = __builtin_fma(E2, E2, DD[m + 2]);
 
-    const double d = IS0 - IS2;
+    const double d = s0 - s2;
     const double t5 = __builtin_fabs(d);
-    const double num = ((IS0 + IS2) - t5) + eps_s;
+    const double num = ((s0 + s2) - t5) - eps_s;
     const double den = t5 + eps_s;
-    const double s0 = IS0 + eps_s, s1 = IS1 + eps_s, s2 = IS2 + eps_s;
     // tau8 (in the units of the scaled indicators) = (2 b)^2, b = D_m - 2 D_{m+1} + D_{m+2};
     // H = tau8 den^2 / 4, G = A num^2 / 4
-    const double b = __builtin_fma(-2.0, D[m + 1], D[m] + D[m + 2]);
+    const double b = e[m] - e[m + 1];
     const double bd = b * den;
     const double H = bd * bd;
     const double G = (Aq * num) * num;
@@ -141,10 +147,10 @@ __device__ __forceinline__ void wzn_window(const double* v, double* fh, double e
     const double B1 = (s0 * s2) * t1;
     const double B2 = (s0 * s1) * t2;
     const double S = __builtin_fma(6.0, B1, __builtin_fma(3.0, B2, B0));
-    const double x0 = (D[m] - D[m + 1]) * (1.0 / 3.0);
-    const double x2 = (D[m + 1] - D[m + 2]) * 0.5;
+    const double x0 = e[m] * (1.0 / 3.0);
+    const double x2 = e[m + 1] * 0.5;
     const double nr = __builtin_fma(B0, x0, B2 * x2);
-    const double base = __builtin_fma(-1.0 / 6.0, D[m + 1], 0.5 * (v[m + 2] + v[m + 3]));
+    const double base = __builtin_fma(-1.0 / 6.0, D[m + 1], __builtin_fma(0.5, g[m + 2], v[m + 2]));
     fh[m] = base + approx_div(nr, S);
   }
 }

@@ -33,11 +33,10 @@ inline Workspace make_workspace(void* ws) {
 struct Tuning1D {
   int nt;      // threads per workgroup
   int k;       // consecutive cells (interfaces) per thread
-  int layout;  // ROW_LDS_TILE: workgroup tile staged in LDS (both signs of the split flux at
-               // once); ROW_WAVE_RUNS: one run per wave; ROW_LDS_SPLIT: LDS tile, one sign of
-               // the split flux at a time
+  int layout;  // ROW_LDS_TILE: both signs of the split flux staged in LDS at once;
+               // ROW_LDS_SPLIT: one sign at a time (half the LDS)
 };
-enum { ROW_LDS_TILE = 0, ROW_WAVE_RUNS = 1, ROW_LDS_SPLIT = 2 };
+enum { ROW_LDS_TILE = 0, ROW_LDS_SPLIT = 1 };
 Tuning1D tuning_1d(int nv, int64_t n);
 
 int set_error(int code, const char* fmt, ...);

@@ -9,7 +9,6 @@
 #include "wzn_host.hpp"
 #include "wzn_rows.hpp"
 #include "wzn_tile.hpp"
-#include "wzn_wave.hpp"
 
 namespace wzn {
 
@@ -19,7 +18,7 @@ template <int NT, int K, int SYS, typename T, bool SPLIT, bool SPEED>
 __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T* W = reinterpret_cast<T*>(lds_raw);
-  __shared__ T EX[2 * SysInfo<SYS>::NV];
+  __shared__ T EX[tile_ex_elems<SYS, NT>()];
   __shared__ double red[NT / 64];
   const int tid = threadIdx.x;
 
@@ -52,38 +51,6 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
   }
 }
 
-// Wave-run variant: every wave of the workgroup evaluates its own run of 64*K cells
-// (wzn_wave.hpp); no LDS staging and no barrier.  Same arithmetic, same results.
-template <int NW, int K, int SYS, typename T, bool SPEED>
-__global__ __launch_bounds__(64 * NW) void wave_kernel(RowArgs<T> a) {
-  const int lane = threadIdx.x & 63;
-  double alpha_d;
-  if (a.alpha_slot) alpha_d = slot_value(a.alpha_slot);
-  else if (a.alpha_arr) alpha_d = a.alpha_arr[0];
-  else alpha_d = a.alpha_const;
-  double dt = 0.0;
-  if (a.mode == MODE_STAGE) {
-    if (a.dt_arr) dt = a.dt_arr[0];
-    else if (a.dt_speed_slot) dt = a.cfl * a.dx / slot_value(a.dt_speed_slot);
-    else dt = a.dt_slot_read[0];
-  }
-  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
-    if (a.dt_slot_write) a.dt_slot_write[0] = dt;
-    if (a.dt_rec) a.dt_rec[0] = dt;
-    if (a.alpha_rec) a.alpha_rec[0] = alpha_d;
-    if (a.slot_zero) a.slot_zero[0] = 0ull;
-  }
-  const int64_t g0 = ((int64_t)blockIdx.x * NW + (threadIdx.x >> 6)) * (64 * K);
-  if (g0 >= a.n) return;  // a whole wave past the row end (no barrier follows)
-  const int64_t rowoff = (int64_t)blockIdx.y * a.row_stride;
-  double smax = 0.0;
-  wave_run<K, SYS, T, SPEED>(a, g0, rowoff, T(alpha_d), dt, smax);
-  if constexpr (SPEED) {
-    smax = wave_max(smax);
-    if (lane == 0) atomic_max_pos(a.speed_next, smax);
-  }
-}
-
 // ------------------------------------------------------------------ host side
 template <int NT, int K, int SYS, typename T, bool SPLIT, bool SPEED>
 static int launch_row_ts(const RowArgs<T>& a, int64_t rows, hipStream_t s) {
@@ -113,38 +80,8 @@ static int launch_row_t(const RowArgs<T>& a, int64_t rows, hipStream_t s) {
   return launch_row_ts<NT, K, SYS, T, SPLIT, false>(a, rows, s);
 }
 
-template <int NW, int K, int SYS, typename T>
-static int launch_wave_t(const RowArgs<T>& a, int64_t rows, hipStream_t s) {
-  const int64_t runs = (a.n + 64 * K - 1) / (64 * K);
-  const int64_t blocks = (runs + NW - 1) / NW;
-  if (blocks > 0x7fffffff || rows > 65535)
-    return set_error(WZN_ERR_SIZE, "grid too large for the wave kernel");
-  if (a.speed_next && SYS == SYS_EULER1)
-    hipLaunchKernelGGL((wave_kernel<NW, K, SYS, T, SYS == SYS_EULER1>),
-                       dim3((unsigned)blocks, (unsigned)rows), dim3(64 * NW), 0, s, a);
-  else
-    hipLaunchKernelGGL((wave_kernel<NW, K, SYS, T, false>), dim3((unsigned)blocks, (unsigned)rows),
-                       dim3(64 * NW), 0, s, a);
-  return check_launch("wave_kernel");
-}
-
 int launch_rows(const RowArgs<double>& a, int sys, int64_t rows, const Tuning1D& tn,
                 hipStream_t s) {
-  if (tn.layout == ROW_WAVE_RUNS) {
-    if (sys == SYS_EULER1) {
-      if (tn.nt == 256 && tn.k == 4) return launch_wave_t<4, 4, SYS_EULER1, double>(a, rows, s);
-      if (tn.nt == 256 && tn.k == 2) return launch_wave_t<4, 2, SYS_EULER1, double>(a, rows, s);
-      if (tn.nt == 64 && tn.k == 4) return launch_wave_t<1, 4, SYS_EULER1, double>(a, rows, s);
-      if (tn.nt == 64 && tn.k == 2) return launch_wave_t<1, 2, SYS_EULER1, double>(a, rows, s);
-      return set_error(WZN_ERR_ARG, "unsupported 1D wave tuning (nt=%d, k=%d)", tn.nt, tn.k);
-    }
-    if (sys == SYS_ADV) {
-      if (tn.nt == 256 && tn.k == 4) return launch_wave_t<4, 4, SYS_ADV, double>(a, rows, s);
-      return set_error(WZN_ERR_ARG, "unsupported advection wave tuning (nt=%d, k=%d)", tn.nt,
-                       tn.k);
-    }
-    return set_error(WZN_ERR_ARG, "no wave layout for this system");
-  }
   if (tn.layout == ROW_LDS_SPLIT) {
     if (sys == SYS_EULER1) {
       if (tn.nt == 256 && tn.k == 4) return launch_row_t<256, 4, SYS_EULER1, double, true>(a, rows, s);

@@ -17,8 +17,8 @@
 // of local cells tK .. tK+K-1 on a register sliding window, and the tile's left boundary
 // interface (right interface of local cell -1) is computed by 2*NV lanes of wave 0, one
 // (component, sign) reconstruction each.  Split fluxes are staged in LDS in a transposed
-// layout (position p -> (p mod K) * LD + p / K) so that lane t reading position t*K + m hits
-// consecutive words for every m.
+// layout (position p -> (p mod K) * LD + p / K) so that lane t writing or reading position
+// t*K + m hits consecutive words for every m.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -88,15 +88,85 @@ __device__ __forceinline__ double wave_speed_1d(const double* U, double adv, dou
   }
 }
 
+// Boundary conditions as an index map (Sec. 4.2, eq:26) for an in-row cell index g in
+// [-3, n + 2] (harmlessly clamped beyond): periodic wrap or transmissive copy of the edge cell.
+// Row lengths are below 2^31 (checked by the host).
+__device__ __forceinline__ int bc_cell(int g, int n, int bc) {
+  if (bc == 0) g = g < 0 ? g + n : (g >= n ? g - n : g);
+  return min(max(g, 0), n - 1);
+}
+
 // TVD-RK3 stage combination (Sec. 4) out = a_s U^n + b_s (U + dt L), evaluated as
 // fma(b_s dt, L, base) with base = fma(a_s, U^n, b_s U) (base = U in the first stage, where
 // a_s = 0, b_s = 1 and no U^n is read).  `ok` = false skips the U^n read (cells past the row).
 template <typename T>
-__device__ __forceinline__ T stage_base(const RowArgs<T>& a, T U, int64_t un_index, bool ok) {
+__device__ __forceinline__ T stage_base(const RowArgs<T>& a, T U, const T* un, bool ok) {
   const T b = T(a.rk_b) * U;
   if (!a.un) return b;
-  const T un = ok ? a.un[un_index] : T(0);
-  return fma_t(T(a.rk_a), un, b);
+  const T v = ok ? *un : T(0);
+  return fma_t(T(a.rk_a), v, b);
+}
+
+// K consecutive elements from p (16-byte vector accesses when `vec`).
+template <int K, typename T>
+__device__ __forceinline__ void load_run(const T* p, T (&d)[K], bool vec) {
+  if constexpr (sizeof(T) == 8 && K % 2 == 0) {
+    if (vec) {
+      typedef double v2d __attribute__((ext_vector_type(2)));
+#pragma unroll
+      for (int j = 0; j < K / 2; ++j) {
+        const v2d t = reinterpret_cast<const v2d*>(p)[j];
+        d[2 * j] = t.x;
+        d[2 * j + 1] = t.y;
+      }
+      return;
+    }
+  }
+  if constexpr (sizeof(T) == 4 && K % 4 == 0) {
+    if (vec) {
+#pragma unroll
+      for (int j = 0; j < K / 4; ++j) {
+        const float4 t = reinterpret_cast<const float4*>(p)[j];
+        d[4 * j] = t.x;
+        d[4 * j + 1] = t.y;
+        d[4 * j + 2] = t.z;
+        d[4 * j + 3] = t.w;
+      }
+      return;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < K; ++j) d[j] = p[j];
+}
+
+// Stores are non-temporal (streaming): the stage output is not re-read by this kernel, and
+// lines that stay dirty in L2 must be written back when the kernel ends.
+template <int K, typename T>
+__device__ __forceinline__ void store_run(T* p, const T (&d)[K], bool vec) {
+  if constexpr (sizeof(T) == 8 && K % 2 == 0) {
+    if (vec) {
+      typedef double v2d __attribute__((ext_vector_type(2)));
+#pragma unroll
+      for (int j = 0; j < K / 2; ++j) {
+        const v2d t = {d[2 * j], d[2 * j + 1]};
+        __builtin_nontemporal_store(t, reinterpret_cast<v2d*>(p) + j);
+      }
+      return;
+    }
+  }
+  if constexpr (sizeof(T) == 4 && K % 4 == 0) {
+    if (vec) {
+      typedef float v4f __attribute__((ext_vector_type(4)));
+#pragma unroll
+      for (int j = 0; j < K / 4; ++j) {
+        const v4f t = {d[4 * j], d[4 * j + 1], d[4 * j + 2], d[4 * j + 3]};
+        __builtin_nontemporal_store(t, reinterpret_cast<v4f*>(p) + j);
+      }
+      return;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < K; ++j) __builtin_nontemporal_store(d[j], p + j);
 }
 
 template <int NT, int K>
@@ -113,77 +183,120 @@ __device__ __forceinline__ int tpos(int p) {
 }
 
 // LDS of one tile: split fluxes of every component and both signs (SPLIT = false), or of one
-// sign at a time (SPLIT = true: the two signs are staged and reconstructed one after the other,
-// halving the footprint at the price of a second flux evaluation per cell).  The interface
-// fluxes reuse the same space (NV arrays).
+// sign at a time (SPLIT = true: w^+ is staged and reconstructed, then every slot is turned into
+// w^- = w^+ - 2 alpha U in place and reconstructed; half the footprint).
 template <int NT, int K, int SYS, typename T, bool SPLIT = false>
 constexpr size_t tile_lds_bytes() {
   return sizeof(T) * (size_t)((SPLIT ? 1 : 2) * SysInfo<SYS>::NV) * Tile<NT, K>::SZ;
 }
 
-// Process the tile whose local cell 0 is global cell g0 of the row starting at element
-// `rowoff` of every component plane.  W: dynamic LDS of tile_lds_bytes(); EX: 2*NV
-// elements of LDS.  All threads of the workgroup must call it (it contains barriers).
+// LDS elements of the small per-tile array EX: 2*NV boundary interface values, 6*NV halo-cell
+// states (second phase of the split layout) and NV per wave (last interface flux of the wave).
+template <int SYS, int NT>
+constexpr int tile_ex_elems() { return (8 + NT / 64) * SysInfo<SYS>::NV; }
+
+// Process the tile whose local cell 0 is cell g0 of the row starting at element `rowoff` of
+// every component plane.  Thread t loads, reconstructs and stores the K consecutive local cells
+// tK .. tK+K-1 (threads 0..5 also stage one halo cell each); split fluxes are staged in LDS at
+// position p = local cell + 3.  The left interface flux of a thread's first cell is the last
+// interface of the previous lane (cross-lane permute), of the previous wave (LDS) or, for the
+// tile's first cell, the boundary interface.  W: dynamic LDS of tile_lds_bytes(); EX: LDS of
+// tile_ex_elems() elements.  All threads of the workgroup must call it (it contains barriers).
 template <int NT, int K, int SYS, typename T, bool SPEED, bool SPLIT = false>
-__device__ __forceinline__ void row_tile(const RowArgs<T>& a, int64_t g0, int64_t rowoff,
+__device__ __forceinline__ void row_tile(const RowArgs<T>& a, int64_t g0l, int64_t rowoff,
                                          T alpha, double dt, T* W, T* EX, double& smax) {
   using TL = Tile<NT, K>;
   constexpr int TT = TL::T;
   constexpr int NV = SysInfo<SYS>::NV;
-  constexpr int NS = SPLIT ? 1 : 2;       // signs staged per phase
-  constexpr int NPH = SPLIT ? 2 : 1;      // phases
-  const int tid = threadIdx.x;
-  const int64_t n = a.n;
+  constexpr int NS = SPLIT ? 1 : 2;   // signs staged per phase
+  constexpr int NPH = SPLIT ? 2 : 1;  // phases
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int n = (int)a.n;
+  const int g0 = (int)g0l;
   const T gm1 = T(a.gamma) - T(1);
   const T adv = T(a.adv);
   const T eps_s = T(a.eps_s), A = window_const<T>(a.A);
+  const T m2a = -T(2) * alpha;
+  const int c0 = g0 + tid * K;          // first own cell
+  const bool full = g0 + TT <= n;       // every own cell is a row cell (uniform)
+  T* HU = EX + 2 * NV;                  // [6][NV] halo cells' U
+  T* XF = EX + 8 * NV;                  // [NT/64][NV] last interface flux of each wave
 
   T Ureg[K][NV];
   T fh[NV][K];
 #pragma unroll
   for (int ph = 0; ph < NPH; ++ph) {
     __syncthreads();  // LDS is free (previous tile or phase has finished reading it)
-    // ---- load (first phase; main rounds keep the cell state in registers for the epilogue
-    //      and the second phase), flux, split
-#pragma unroll
-    for (int r = 0; r <= K; ++r) {
-      int p;
-      if (r < K) p = 3 + tid + NT * r;                     // local cells 0 .. T-1
-      else p = tid < 3 ? tid : (tid < 6 ? TT + tid : -1);  // cells -3,-2,-1, T,T+1,T+2
-      if (r == K && p < 0) break;
-      T U[NV], F[NV];
-      if (ph == 0 || r == K) {
-        const int64_t gi = rowoff + bc_index(g0 + p - 3, n, a.bc);
-#pragma unroll
-        for (int c = 0; c < NV; ++c) U[c] = a.uin[c * a.plane + gi];
-      } else {
-        // the second phase evaluates the flux again (not kept from the first phase, which
-        // would hold NV*K more values across the whole reconstruction); the empty asm keeps
-        // the compiler from reusing the first phase's results
-#pragma unroll
-        for (int c = 0; c < NV; ++c) {
-          U[c] = Ureg[r][c];
-          asm volatile("" : "+v"(U[c]));
-        }
-      }
-      row_flux<SYS, T>(U, F, adv, gm1);
-      const int q = tpos<NT, K>(p);
+    if (ph == 0) {
+      // ---- own cells: load, flux, split.  w^+ = F + alpha U, w^- = w^+ - 2 alpha U in every
+      //      layout, so that the split layout forms w^- from the staged w^+ with the same bits.
 #pragma unroll
       for (int c = 0; c < NV; ++c) {
-        if (!SPLIT || ph == 0) W[(NS * c) * TL::SZ + q] = fma_t(alpha, U[c], F[c]);
-        if (!SPLIT || ph == 1) W[(NS * c + NS - 1) * TL::SZ + q] = fma_t(-alpha, U[c], F[c]);
-      }
-      if (ph == 0 && r < K) {
+        const T* up = a.uin + c * a.plane + rowoff;
+        T u[K];
+        if (full) {
+          load_run<K, T>(up + c0, u, ((uintptr_t)(up + g0) & 15) == 0);
+        } else {
 #pragma unroll
-        for (int c = 0; c < NV; ++c) Ureg[r][c] = U[c];
-      }
-      if (SPLIT && ph == 1 && r < K && a.mode == MODE_STAGE) {
-        // U is not needed past this point: replace it by the stage base a_s U^n + b_s U
-        // (the U^n read is issued here, mid-kernel, rather than in the epilogue)
-        const int64_t gcell = g0 + p - 3;
+          for (int j = 0; j < K; ++j) u[j] = up[bc_cell(c0 + j, n, a.bc)];
+        }
 #pragma unroll
-        for (int c = 0; c < NV; ++c)
-          Ureg[r][c] = stage_base<T>(a, Ureg[r][c], c * a.plane + rowoff + gcell, gcell < n);
+        for (int j = 0; j < K; ++j) Ureg[j][c] = u[j];
+      }
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        T F[NV];
+        row_flux<SYS, T>(Ureg[j], F, adv, gm1);
+        const int q = tpos<NT, K>(3 + tid * K + j);
+#pragma unroll
+        for (int c = 0; c < NV; ++c) {
+          const T wp = fma_t(alpha, Ureg[j][c], F[c]);
+          W[(NS * c) * TL::SZ + q] = wp;
+          if (!SPLIT) W[(NS * c + 1) * TL::SZ + q] = fma_t(m2a, Ureg[j][c], wp);
+        }
+      }
+      // ---- halo cells -3, -2, -1, T, T+1, T+2 on threads 0..5
+      if (tid < 6) {
+        const int p = tid < 3 ? tid : TT + tid;
+        const int cell = bc_cell(g0 + p - 3, n, a.bc);
+        T U[NV], F[NV];
+#pragma unroll
+        for (int c = 0; c < NV; ++c) U[c] = a.uin[c * a.plane + rowoff + cell];
+        row_flux<SYS, T>(U, F, adv, gm1);
+        const int q = tpos<NT, K>(p);
+#pragma unroll
+        for (int c = 0; c < NV; ++c) {
+          const T wp = fma_t(alpha, U[c], F[c]);
+          W[(NS * c) * TL::SZ + q] = wp;
+          if (!SPLIT) W[(NS * c + 1) * TL::SZ + q] = fma_t(m2a, U[c], wp);
+          else HU[tid * NV + c] = U[c];
+        }
+      }
+    } else {
+      // ---- second phase of the split layout: w^- from the staged w^+ of the same slot
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        const int q = tpos<NT, K>(3 + tid * K + j);
+#pragma unroll
+        for (int c = 0; c < NV; ++c) W[c * TL::SZ + q] = fma_t(m2a, Ureg[j][c], W[c * TL::SZ + q]);
+      }
+      if (tid < 6) {
+        const int q = tpos<NT, K>(tid < 3 ? tid : TT + tid);
+#pragma unroll
+        for (int c = 0; c < NV; ++c) W[c * TL::SZ + q] = fma_t(m2a, HU[tid * NV + c], W[c * TL::SZ + q]);
+      }
+      if (a.mode == MODE_STAGE) {
+        // U is not needed past this point: replace it by the stage base a_s U^n + b_s U (the
+        // U^n read is issued here, mid-kernel, rather than in the epilogue)
+#pragma unroll
+        for (int c = 0; c < NV; ++c) {
+          const T* unp = a.un ? a.un + c * a.plane + rowoff + c0 : nullptr;
+#pragma unroll
+          for (int j = 0; j < K; ++j) {
+            Ureg[j][c] = stage_base<T>(a, Ureg[j][c], unp + j, c0 + j < n);
+            asm volatile("" : "+v"(Ureg[j][c]));  // combine here, not in the epilogue
+          }
+        }
       }
     }
     __syncthreads();
@@ -214,9 +327,9 @@ __device__ __forceinline__ void row_tile(const RowArgs<T>& a, int64_t g0, int64_
 #pragma unroll
         for (int m = 0; m < K; ++m) {
           fh[c][m] = h[m];
-          // materialise here: otherwise the compiler sinks the last steps of the window into
-          // the second phase and keeps the window values alive across it
-          if (SPLIT) asm volatile("" : "+v"(fh[c][m]));
+          // materialise here: otherwise the compiler sinks the last steps of the window past
+          // the following barriers and keeps the window values alive across them
+          asm volatile("" : "+v"(fh[c][m]));
         }
       }
       if (!SPLIT || ph == 1) {
@@ -228,43 +341,68 @@ __device__ __forceinline__ void row_tile(const RowArgs<T>& a, int64_t g0, int64_
         }
         wzn_window<K>(v, h, eps_s, A);
 #pragma unroll
-        for (int m = 0; m < K; ++m) fh[c][m] += h[K - 1 - m];
+        for (int m = 0; m < K; ++m) {
+          fh[c][m] += h[K - 1 - m];
+          asm volatile("" : "+v"(fh[c][m]));
+        }
       }
     }
   }
-  __syncthreads();  // all windows read; reuse LDS for the interface fluxes
-  T* FH = W;        // [NV][SZ], indexed by local cell e in the transposed layout
-#pragma unroll
-  for (int c = 0; c < NV; ++c)
-#pragma unroll
-    for (int m = 0; m < K; ++m) FH[c * TL::SZ + m * TL::LD + tid] = fh[c][m];
-  __syncthreads();
 
-  // ---- epilogue on the loader mapping: local cell e = tid + NT r
+  // ---- left interface flux of the thread's first cell
+  if (lane == 63) {
+#pragma unroll
+    for (int c = 0; c < NV; ++c) XF[wave * NV + c] = fh[c][K - 1];
+  }
+  __syncthreads();
+  T fl0[NV];
+#pragma unroll
+  for (int c = 0; c < NV; ++c) {
+    const T prev = __shfl_up(fh[c][K - 1], 1, 64);
+    fl0[c] = lane != 0 ? prev
+                       : (wave == 0 ? EX[2 * c] + EX[2 * c + 1] : XF[(wave - 1) * NV + c]);
+  }
+
+  // ---- flux difference, stage combination, store, wave speed of the output
   const T coef = T(-0.5 / a.dx);
+  const T cdt = T(a.rk_b * dt);
+  T O[NV][K];
 #pragma unroll
-  for (int r = 0; r < K; ++r) {
-    const int e = tid + NT * r;
-    const int64_t gcell = g0 + e;
-    if (gcell >= n) continue;
-    double O[NV];
+  for (int c = 0; c < NV; ++c) {
+    T o[K];
 #pragma unroll
-    for (int c = 0; c < NV; ++c) {
-      const T fr = FH[c * TL::SZ + tpos<NT, K>(e)];
-      const T fl = e > 0 ? FH[c * TL::SZ + tpos<NT, K>(e - 1)] : EX[2 * c] + EX[2 * c + 1];
-      const T L = coef * (fr - fl);
-      T o;
+    for (int m = 0; m < K; ++m) {
+      const T L = coef * (fh[c][m] - (m == 0 ? fl0[c] : fh[c][m - 1]));
       if (a.mode == MODE_RHS) {
-        o = L;
+        o[m] = L;
       } else {
-        const T base = SPLIT ? Ureg[r][c]
-                             : stage_base<T>(a, Ureg[r][c], c * a.plane + rowoff + gcell, true);
-        o = fma_t(T(a.rk_b * dt), L, base);
+        const T base = SPLIT ? Ureg[m][c]
+                             : stage_base<T>(a, Ureg[m][c],
+                                             a.un ? a.un + c * a.plane + rowoff + c0 + m : nullptr,
+                                             c0 + m < n);
+        o[m] = fma_t(cdt, L, base);
       }
-      a.out[c * a.plane + rowoff + gcell] = o;
-      O[c] = double(o);
+      O[c][m] = o[m];
     }
-    if constexpr (SPEED && SYS != SYS_EULER2X) smax = fmax(smax, wave_speed_1d<SYS>(O, a.adv, a.gamma));
+    T* op = a.out + c * a.plane + rowoff;
+    if (full) {
+      store_run<K, T>(op + c0, o, ((uintptr_t)(op + g0) & 15) == 0);
+    } else {
+#pragma unroll
+      for (int m = 0; m < K; ++m)
+        if (c0 + m < n) op[c0 + m] = o[m];
+    }
+  }
+  if constexpr (SPEED && SYS != SYS_EULER2X) {
+#pragma unroll
+    for (int m = 0; m < K; ++m) {
+      if (c0 + m < n) {
+        double S[NV];
+#pragma unroll
+        for (int c = 0; c < NV; ++c) S[c] = double(O[c][m]);
+        smax = fmax(smax, wave_speed_1d<SYS>(S, a.adv, a.gamma));
+      }
+    }
   }
 }
 

@@ -1,8 +1,7 @@
 """GPU checks that every launch shape of the 1D row kernel gives the same bits.
 
-The LDS-tile layout (one workgroup tile staged in LDS), its split variant (the two signs of
-the split flux staged one after the other) and the wave-run layout (one run of 64 k cells per
-wave, neighbours exchanged across lanes) evaluate the same arithmetic in the same order, so a right-hand side and a short TVD-RK3 run must agree bit for bit across all
+The LDS-tile layout (one workgroup tile staged in LDS) and its split variant (the two signs of
+the split flux staged one after the other) evaluate the same arithmetic in the same order, so a right-hand side and a short TVD-RK3 run must agree bit for bit across all
 shapes, and with the CPU oracle to the parity tolerances, on ragged sizes (runs and tiles
 that end inside the row, rows shorter than one run) and both boundary conditions.
 """
@@ -16,8 +15,7 @@ pytestmark = pytest.mark.gpu
 RHS_TOL = 1e-12
 RUN_TOL = 1e-10
 SHAPES = [(256, 4, 0), (256, 2, 0), (256, 1, 0), (128, 4, 0), (128, 8, 0), (64, 8, 0),
-          (64, 4, 0), (64, 2, 0), (64, 1, 0), (256, 4, 1), (256, 2, 1), (64, 4, 1), (64, 2, 1),
-          (256, 4, 2), (256, 2, 2), (128, 4, 2), (64, 4, 2)]
+          (64, 4, 0), (64, 2, 0), (64, 1, 0), (256, 4, 1), (256, 2, 1), (128, 4, 1), (64, 4, 1)]
 
 
 @pytest.fixture(scope="module")
@@ -76,26 +74,9 @@ def test_euler_shapes_agree(api, orc, n, bc):
     autotune.set_row_tuning(0, 0)
 
 
-@pytest.mark.parametrize("n", [200, 255, 1031])
-def test_advection_layouts_agree(api, orc, n):
-    from paper_2004_07954_amd import autotune
-    note("row layouts advection", n)
-    u0, dx = I.advection_smooth(n)
-    u0 = u0 + 0.3 * (np.abs(I.cell_centres(-1, 1, n)[0]) < 0.25)
-    r, _ = orc.rhs_1d(u0, dx, sys=orc.SYS_ADV, bc=orc.BC_PERIODIC)
-    prm = api.params("advection", bc="periodic")
-    outs = []
-    for shape in [(64, 4, 0), (256, 4, 1)]:
-        autotune.set_row_tuning(*shape)
-        outs.append(api.rhs_1d(to_dev(u0), dx, prm).cpu().numpy())
-    autotune.set_row_tuning(0, 0)
-    assert normwise(outs[0], r) <= RHS_TOL
-    np.testing.assert_array_equal(outs[1], outs[0])
-
-
 def test_row_tuning_rejects_unknown_shapes(api):
     from paper_2004_07954_amd import autotune
     from paper_2004_07954_amd._lib import WznError
-    for shape in [(96, 4, 0), (256, 8, 1), (128, 4, 1), (64, 2, 2), (256, 4, 3)]:
+    for shape in [(96, 4, 0), (256, 8, 1), (128, 8, 1), (64, 2, 1), (256, 4, 2)]:
         with pytest.raises(WznError):
             autotune.set_row_tuning(*shape)
