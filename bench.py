@@ -36,19 +36,29 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def committed_traffic(kernel, workload):
-    """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it was taken on
-    the current kernel sources (else None)."""
-    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.md" % (kernel, workload))
+def committed_profile(kind, kernel, workload, key):
+    """A figure from a committed rocprofv3 --pmc summary (profiles/<kind>_<kernel>_<workload>.md,
+    line '<KIND>_JSON {...}'), if it was taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "%s_%s_%s.md" % (kind, kernel, workload))
     if not os.path.exists(path):
         return None
     rec = None
+    tag = kind.upper() + "_JSON "
     for line in open(path):
-        if line.startswith("TRAFFIC_JSON "):
-            rec = json.loads(line[len("TRAFFIC_JSON "):])
+        if line.startswith(tag):
+            rec = json.loads(line[len(tag):])
     if rec is None or rec.get("source_hash") != kernel_source_hash():
         return None
-    return rec.get("hbm_bytes_per_launch")
+    return rec.get(key)
+
+
+# Algorithmic fp64 flops of one 1D Euler cell-stage, counted on the scheme's literal formulas
+# (+, -, *, / and a square root one flop each): 6 reconstructions of 86 (indicators 33, tau5 1,
+# tau8 8, C 7, alpha 12, normalisation 5, candidate polynomials 15, combination 5), flux 10,
+# Lax-Friedrichs split 15, flux difference 9, stage combination 12 (mean of 6, 15, 15) and
+# the wave speed for the next alpha and dt 11.
+FLOPS_PER_CELL_STAGE = 6 * 86 + 10 + 15 + 9 + 12 + 11
+VALU_LANE_PEAK = 256 * 4 * 16 * 2.4e9  # fp64 VALU lane-instructions/s (FMA = 1 instruction)
 
 
 def cpu_baseline(n, budget_s=12.0):
@@ -277,7 +287,13 @@ def main():
     bytes_per_launch = n * (48 + 72 + 72) / 3.0
     achieved = bytes_per_launch / (kernel_ms * 1e-3) / 1e9
     value = n * 3 * K / (ms * 1e-3)
-    traffic = committed_traffic("row_kernel", "euler1d_n%d" % n)
+    from paper_2004_07954_amd import autotune
+    nt, kk, lay = autotune.get_row_tuning(3, n)
+    kname = "row_kernel<%d, %d, EULER1, double, %s>" % (nt, kk, "split" if lay == 1 else "tile")
+    workload = "euler1d_n%d" % n
+    traffic = committed_profile("traffic", "row_kernel", workload, "hbm_bytes_per_launch")
+    valu = committed_profile("valu", "row_kernel", workload, "valu_instr_per_cell")
+    flops = FLOPS_PER_CELL_STAGE * n / (kernel_ms * 1e-3) / 1e12
     rec = {
         "metric": "WENO-ZN RHS cell-updates/s (1D Euler, fused TVD-RK3 stages)",
         "value": value,
@@ -296,8 +312,15 @@ def main():
                    "launch": "hip_graph" if graph else "stream", "kernels_per_step": 3},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "kernel": "row_kernel<256,4,EULER1,double>",
-                     "kernel_ms": kernel_ms},
+                     "traffic": traffic, "kernel": kname, "kernel_ms": kernel_ms},
+        # the stage kernel's fp64 VALU side (algorithmic flops of the literal formulas, and the
+        # measured VALU instructions per cell from the committed counter profile)
+        "roofline_alu": {"bound": "alu", "achieved": flops, "peak": FP64_VALU_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": flops / FP64_VALU_PEAK_TFLOPS,
+                         "flops_per_cell_stage": FLOPS_PER_CELL_STAGE,
+                         "valu_instr_per_cell_stage": valu,
+                         "valu_issue_frac": (valu * n / (kernel_ms * 1e-3) / VALU_LANE_PEAK
+                                             if valu else None)},
         "cpu_baseline": None,
     }
     if args.copy_calibration:

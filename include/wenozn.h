@@ -44,7 +44,8 @@ extern "C" {
 enum {
   WZN_OK = 0,
   WZN_ERR_ARG = 1,        /* null pointer, bad parameter value */
-  WZN_ERR_SIZE = 2,       /* grid too small (n, nx, ny must be >= 6) or too large */
+  WZN_ERR_SIZE = 2,       /* grid too small (n, nx, ny must be >= 6) or too large (1D rows
+                             and batched instances <= 2^30 cells, 2D sides <= 2^24) */
   WZN_ERR_DTYPE = 3,      /* unsupported dtype for this entry point */
   WZN_ERR_HIP = 4,        /* a HIP runtime call or kernel launch failed */
   WZN_ERR_UNSUPPORTED = 6 /* parameter combination not implemented on the GPU */
@@ -92,6 +93,11 @@ const char* wzn_last_error(void);
  * do not depend on it (bit for bit).  Returns WZN_ERR_ARG for an unsupported shape. */
 enum { WZN_ROW_LDS_TILE = 0, WZN_ROW_LDS_SPLIT = 1 };
 int32_t wzn_set_row_tuning(int32_t nt, int32_t k, int32_t layout);
+
+/* The launch shape the 1D entry points use for nvar (1: advection, 3: Euler) components of
+ * n cells (the override of wzn_set_row_tuning if set), written to *nt, *k, *layout (host
+ * pointers).  WZN_ERR_ARG for a null pointer or another nvar. */
+int32_t wzn_get_row_tuning(int32_t nvar, int64_t n, int32_t* nt, int32_t* k, int32_t* layout);
 
 /* Bytes of device workspace `ws` needed by any entry point for grids up to nx * ny cells
  * (ny = 1 in 1D).  Currently a small constant. */
@@ -160,7 +166,7 @@ int32_t wzn_rk3_step_2d(const wzn_params* p, void* u, void* stage, int64_t nx, i
  * alphas are always reduced (p->lf_alpha_x must be < 0).
  *   stage    device scratch of 2 * 3 * total doubles.
  *   offsets  device int64 [batch + 1], non-decreasing, offsets[batch] == total; every instance
- *            must have >= 6 cells (shorter or out-of-range instances are skipped unchanged).
+ *            must have 6 .. 2^30 cells (other or out-of-range instances are skipped unchanged).
  *   dx       device double [batch].
  *   order    device int32 [batch]: the order in which instances are handed to workgroups
  *            (longest first balances the load), or NULL for 0 .. batch-1.

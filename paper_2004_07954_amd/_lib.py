@@ -39,6 +39,8 @@ SIGNATURES = [
     ("wzn_status_string", C.c_char_p, [_I32]),
     ("wzn_last_error", C.c_char_p, []),
     ("wzn_set_row_tuning", _I32, [_I32, _I32, _I32]),
+    ("wzn_get_row_tuning", _I32, [_I32, _I64, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                  C.POINTER(C.c_int32)]),
     ("wzn_workspace_bytes", _SZ, [_PP, _I64, _I64]),
     ("wzn_rhs_1d", _I32, [_PP, _P, _P, _I64, _D, _P, _P]),
     ("wzn_rk3_run_1d", _I32, [_PP, _P, _P, _I64, _D, _D, _I32, _P, _P, _P, _P, _P, _P]),

@@ -84,6 +84,15 @@ ROW_SHAPES = [(256, 4, 0), (256, 2, 0), (256, 1, 0), (128, 4, 0), (128, 8, 0), (
               (64, 4, 0), (64, 2, 0), (64, 1, 0), (256, 4, 1), (256, 2, 1), (128, 4, 1), (64, 4, 1)]
 
 
+def get_row_tuning(nvar, n):
+    """(nt, k, layout) the 1D entry points use for nvar components of n cells."""
+    import ctypes as C
+    from ._lib import check, lib
+    nt, k, lay = C.c_int32(), C.c_int32(), C.c_int32()
+    check(lib().wzn_get_row_tuning(int(nvar), int(n), C.byref(nt), C.byref(k), C.byref(lay)))
+    return nt.value, k.value, lay.value
+
+
 def set_row_tuning(nt, k, layout=0):
     from ._lib import check, lib
     check(lib().wzn_set_row_tuning(int(nt), int(k), int(layout)))

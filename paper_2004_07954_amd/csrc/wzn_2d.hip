@@ -8,12 +8,12 @@
 //      combination, and max(|u| + c), max(|v| + c) of the output for the next stage's alphas
 //      and the next step's dt = cfl dtx dty / (dtx + dty) (Sec. 4.4).
 //
-// Column kernel layout: a wave covers 64 consecutive columns (lane = column, so every global
-// access of a row is coalesced); each lane walks down one column segment of S = KY*R - 1
-// rows in R chunks of KY interfaces.  The chunk window (KY + 5 rows) lives in registers
-// together with the primitive state of each row (rho, rho u, rho v, E, v, p), and the five
-// rows shared with the next chunk are carried over instead of reloaded.  The segment's
-// first interface (below its first row) is the one extra interface per segment.
+// Column kernel layout: a workgroup of NG waves walks down a strip of 64 columns (lane =
+// column, so every global access of a row is coalesced), TY = NG*K rows per iteration; the
+// split fluxes of the iteration's rows plus 3 halo rows above and below are staged in LDS one
+// sign at a time, each thread reconstructs the upper interfaces of its K rows on a register
+// window, and the interface between groups and between iterations is passed through LDS, so
+// the only extra interface is the one below a segment's first row.
 #include <hip/hip_runtime.h>
 
 #include "wzn_device.hpp"
@@ -34,7 +34,7 @@ struct ColArgs {
   double dx, dy;
   int bc;
   int mode;
-  int nseg;       // segments along y
+  int seg;        // rows per segment (a multiple of the tile height)
   double rk_a, rk_b;
   double gamma, eps_s, A;
   const unsigned long long* alpha_slot;  // alpha_y
@@ -53,28 +53,58 @@ struct ColArgs {
   unsigned long long* zero_y;
 };
 
-template <typename T>
-struct Prim {
-  T rho, mx, my, E, v, p;
+// Column tile: NG row groups (one 64-lane wave each) of K rows, 64 columns; TY = NG*K rows per
+// iteration plus 3 halo rows above and below staged in LDS.
+template <int NG, int K>
+struct ColTile {
+  static constexpr int TY = NG * K;
+  static constexpr int NPOS = TY + 6;
 };
 
-template <int KY, int R, int NW, typename T>
-__global__ __launch_bounds__(64 * NW)
+// y flux G = (rho v, rho u v, rho v^2 + p, v (E + p)) of a 2D Euler state, through one
+// reciprocal of rho, in a fixed operation order.
+template <typename T>
+__device__ __forceinline__ void flux_y(const T (&U)[4], T (&G)[4], T gm1) {
+#pragma clang fp contract(off)
+  const T r = rcp_nr(U[0]);
+  const T u = U[1] * r, v = U[2] * r;
+  const T p = gm1 * fma_t(-(T(0.5) * U[2]), v, fma_t(-(T(0.5) * U[1]), u, U[3]));
+  G[0] = U[2];
+  G[1] = U[1] * v;
+  G[2] = fma_t(U[2], v, p);
+  G[3] = v * (U[3] + p);
+}
+
+// One workgroup walks down the rows [y_s, y_e) of a strip of 64 columns, TY rows per iteration.
+// Thread (column, group g) loads, reconstructs and finishes rows y0 + gK .. y0 + gK + K - 1 of
+// its column; the split fluxes of all components are staged one sign at a time (w^+ first,
+// then w^- = w^+ - 2 alpha U in place).  The lower interface of a group's first row is the
+// last interface of the group below (LDS), of the previous iteration's last group (carried in
+// LDS), or at the segment's first row the boundary interface, reconstructed once per segment.
+template <int NG, int K, typename T, bool SPEED>
+__global__ __launch_bounds__(64 * NG)
 void col_kernel(ColArgs<T> a) {
-  constexpr int S = KY * R - 1;  // rows per segment
-  constexpr int NPOS = KY + 5;
-  __shared__ double red[2][NW];
-  const int lane = threadIdx.x;
-  const int64_t x = (int64_t)blockIdx.x * 64 + lane;
-  const int64_t xc = x < a.nx ? x : a.nx - 1;
-  const int seg = blockIdx.y * NW + threadIdx.y;
-  const int64_t r0 = (int64_t)seg * S;
+  static_assert(NG >= 4, "the segment's boundary interface uses one group per component");
+  using CT = ColTile<NG, K>;
+  constexpr int TY = CT::TY, NPOS = CT::NPOS;
+  __shared__ T W[4 * NPOS * 64];
+  __shared__ T XF[(NG - 1) * 4 * 64];
+  __shared__ T CARRY[2][4 * 64];
+  __shared__ double red[2][NG];
+  const int col = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int nx = (int)a.nx, ny = (int)a.ny;
+  const int x = blockIdx.x * 64 + col;
+  const bool xin = x < nx;
+  const int xc = xin ? x : nx - 1;
+  const int ys = blockIdx.y * a.seg;
+  const int ye = min(ys + a.seg, ny);
 
   double alpha_d;
   if (a.alpha_slot) alpha_d = slot_value(a.alpha_slot);
   else if (a.alpha_arr) alpha_d = a.alpha_arr[0];
   else alpha_d = a.alpha_const;
   const T alpha = T(alpha_d);
+  const T m2a = -T(2) * alpha;
   double dt = 0.0;
   if (a.mode == MODE_STAGE) {
     if (a.dt_arr) {
@@ -87,7 +117,7 @@ void col_kernel(ColArgs<T> a) {
       dt = a.dt_slot_read[0];
     }
   }
-  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 && threadIdx.y == 0) {
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
     if (a.dt_slot_write) a.dt_slot_write[0] = dt;
     if (a.dt_rec) a.dt_rec[0] = dt;
     if (a.zero_x) a.zero_x[0] = 0ull;
@@ -97,108 +127,178 @@ void col_kernel(ColArgs<T> a) {
   const T gm1 = T(a.gamma) - T(1);
   const T eps_s = T(a.eps_s), A = window_const<T>(a.A);
   const T coef = T(-0.5 / a.dy);
+  const T cdt = a.mode == MODE_STAGE ? T(a.rk_b * dt) : T(1);
   const double gamma = a.gamma;
   double sxm = 0.0, sym = 0.0;
 
-  if (seg < a.nseg) {
-    Prim<T> P[NPOS];
-    T carry[4];
-    for (int ch = 0; ch < R; ++ch) {
-      const int64_t q0 = r0 - 1 + (int64_t)ch * KY;  // first interface row of the chunk
+  T Ureg[K][4];   // own rows: state, then (second phase) the base of the output
+  T HU[2][4];     // halo rows of groups 0..2 (top row g, bottom row TY + 3 + g)
+  T fh[4][K];
+  int it = 0;
+  for (int y0 = ys; y0 < ye; y0 += TY, ++it) {
+    const int par = it & 1;
 #pragma unroll
-      for (int i = 0; i < NPOS; ++i) {
-        if (ch > 0 && i < 5) continue;  // carried over from the previous chunk
-        const int64_t gy = bc_index(q0 - 2 + i, a.ny, a.bc);
-        const int64_t gi = gy * a.nx + xc;
-        Prim<T> q;
-        q.rho = a.uin[gi];
-        q.mx = a.uin[a.plane + gi];
-        q.my = a.uin[2 * a.plane + gi];
-        q.E = a.uin[3 * a.plane + gi];
-        const T r = rcp_nr(q.rho);
-        const T u = q.mx * r;
-        q.v = q.my * r;
-        q.p = gm1 * fma_t(-(T(0.5) * q.my), q.v, fma_t(-(T(0.5) * q.mx), u, q.E));
-        P[i] = q;
+    for (int ph = 0; ph < 2; ++ph) {
+      __syncthreads();  // W, XF and CARRY of the previous phase / iteration are consumed
+      if (ph == 0) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          const int yy = bc_cell(y0 + g * K + j, ny, a.bc);
+          const int64_t gi = (int64_t)yy * nx + xc;
+#pragma unroll
+          for (int c = 0; c < 4; ++c) Ureg[j][c] = a.uin[c * a.plane + gi];
+        }
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          T G[4];
+          flux_y<T>(Ureg[j], G, gm1);
+          const int p = 3 + g * K + j;
+#pragma unroll
+          for (int c = 0; c < 4; ++c) W[(c * NPOS + p) * 64 + col] = fma_t(alpha, Ureg[j][c], G[c]);
+        }
+        if (g < 3) {
+#pragma unroll
+          for (int hh = 0; hh < 2; ++hh) {
+            const int p = hh == 0 ? g : TY + 3 + g;
+            const int yy = bc_cell(y0 + p - 3, ny, a.bc);
+            const int64_t gi = (int64_t)yy * nx + xc;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) HU[hh][c] = a.uin[c * a.plane + gi];
+            T G[4];
+            flux_y<T>(HU[hh], G, gm1);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) W[(c * NPOS + p) * 64 + col] = fma_t(alpha, HU[hh][c], G[c]);
+          }
+        }
+      } else {
+        // w^- from the staged w^+ of the same slot
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          const int p = 3 + g * K + j;
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            T& w = W[(c * NPOS + p) * 64 + col];
+            w = fma_t(m2a, Ureg[j][c], w);
+          }
+        }
+        if (g < 3) {
+#pragma unroll
+          for (int hh = 0; hh < 2; ++hh) {
+            const int p = hh == 0 ? g : TY + 3 + g;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+              T& w = W[(c * NPOS + p) * 64 + col];
+              w = fma_t(m2a, HU[hh][c], w);
+            }
+          }
+        }
+        // the state is not needed past this point: replace it by the base of the output,
+        // Lx (RHS) or fma(b_s dt, Lx, fma(a_s, U^n, b_s U)) (stage), so that the output is
+        // fma(cdt, Ly, base) with cdt = 1 or b_s dt
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          const int y = y0 + g * K + j;
+          const bool ok = y < ye && xin;
+          const int64_t gi = (int64_t)(ok ? y : ys) * nx + xc;
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const T lx = ok ? a.lx[c * a.plane + gi] : T(0);
+            T base = lx;
+            if (a.mode == MODE_STAGE) {
+              T b = T(a.rk_b) * Ureg[j][c];
+              if (a.un) b = fma_t(T(a.rk_a), ok ? a.un[c * a.plane + gi] : T(0), b);
+              base = fma_t(cdt, lx, b);
+            }
+            Ureg[j][c] = base;
+            asm volatile("" : "+v"(Ureg[j][c]));  // combine here, not in the epilogue
+          }
+        }
       }
-      // per component: reconstruct the KY top interfaces, then finish the KY rows
+      __syncthreads();
+
+      // the segment's boundary interface (below its first row): group c < 4 reconstructs
+      // component c, sign ph; carried in as the previous iteration's last interface
+      if (it == 0 && g < 4) {
+        T v[5], h[1];
+#pragma unroll
+        for (int i = 0; i < 5; ++i) v[i] = W[(g * NPOS + (ph == 0 ? i : 5 - i)) * 64 + col];
+        wzn_window<1>(v, h, eps_s, A);
+        if (ph == 0) CARRY[1][g * 64 + col] = h[0];
+        else CARRY[1][g * 64 + col] += h[0];
+      }
+
+      // windows: thread (col, g) owns the upper interfaces of rows gK .. gK+K-1
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        T G[NPOS], Uc[NPOS];
+        T v[K + 4], h[K];
+        if (ph == 0) {
 #pragma unroll
-        for (int i = 0; i < NPOS; ++i) {
-          const Prim<T>& q = P[i];
-          if (c == 0) { G[i] = q.my; Uc[i] = q.rho; }
-          else if (c == 1) { G[i] = q.mx * q.v; Uc[i] = q.mx; }
-          else if (c == 2) { G[i] = fma_t(q.my, q.v, q.p); Uc[i] = q.my; }
-          else { G[i] = q.v * (q.E + q.p); Uc[i] = q.E; }
-        }
-        T w[KY + 4], h[KY], fh[KY];
+          for (int i = 0; i < K + 4; ++i) v[i] = W[(c * NPOS + g * K + 1 + i) * 64 + col];
+          wzn_window<K>(v, h, eps_s, A);
 #pragma unroll
-        for (int i = 0; i < KY + 4; ++i) w[i] = fma_t(alpha, Uc[i], G[i]);
-        wzn_window<KY>(w, h, eps_s, A);
-#pragma unroll
-        for (int m = 0; m < KY; ++m) fh[m] = h[m];
-#pragma unroll
-        for (int i = 0; i < KY + 4; ++i) w[i] = fma_t(-alpha, Uc[KY + 4 - i], G[KY + 4 - i]);
-        wzn_window<KY>(w, h, eps_s, A);
-#pragma unroll
-        for (int m = 0; m < KY; ++m) fh[m] += h[KY - 1 - m];
-        // rows q0 + m: bottom interface fh[m-1] (or the one carried from the last chunk)
-#pragma unroll
-        for (int m = 0; m < KY; ++m) {
-          const int64_t y = q0 + m;
-          const bool active = (ch > 0 || m > 0) && y < r0 + S && y < a.ny && x < a.nx;
-          if (active) {
-            const int64_t gi = y * a.nx + x;
-            const T lo = m > 0 ? fh[m - 1] : carry[c];
-            const T L = a.lx[c * a.plane + gi] + coef * (fh[m] - lo);
-            T o;
-            if (a.mode == MODE_RHS) {
-              o = L;
-            } else {
-              T v = Uc[m + 2] + T(dt) * L;
-              if (a.un) v = fma_t(T(a.rk_a), a.un[c * a.plane + gi], T(a.rk_b) * v);
-              o = v;
-            }
-            a.out[c * a.plane + gi] = o;
+          for (int m = 0; m < K; ++m) {
+            fh[c][m] = h[m];
+            asm volatile("" : "+v"(fh[c][m]));
           }
-        }
-        carry[c] = fh[KY - 1];
-      }
-      if (a.speed_next_x) {
+        } else {
 #pragma unroll
-        for (int m = 0; m < KY; ++m) {
-          const int64_t y = q0 + m;
-          const bool active = (ch > 0 || m > 0) && y < r0 + S && y < a.ny && x < a.nx;
-          if (active) {
-            // the thread re-reads the four components it has just written
-            const int64_t gi = y * a.nx + x;
-            const double o0 = a.out[gi], o1 = a.out[a.plane + gi];
-            const double o2 = a.out[2 * a.plane + gi], o3 = a.out[3 * a.plane + gi];
-            double ax, ay;
-            wave_speeds_2d(o0, o1, o2, o3, gamma, ax, ay);
-            sxm = fmax(sxm, ax);
-            sym = fmax(sym, ay);
+          for (int i = 0; i < K + 4; ++i) v[i] = W[(c * NPOS + g * K + K + 5 - i) * 64 + col];
+          wzn_window<K>(v, h, eps_s, A);
+#pragma unroll
+          for (int m = 0; m < K; ++m) {
+            fh[c][m] += h[K - 1 - m];
+            asm volatile("" : "+v"(fh[c][m]));
           }
         }
       }
-#pragma unroll
-      for (int i = 0; i < 5; ++i) P[i] = P[i + KY];
     }
-  }
-  if (a.speed_next_x) {
-    sxm = wave_max(sxm);
-    sym = wave_max(sym);
-    if (lane == 0) {
-      red[0][threadIdx.y] = sxm;
-      red[1][threadIdx.y] = sym;
+    // ---- exchange the groups' last interfaces
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      if (g < NG - 1) XF[(g * 4 + c) * 64 + col] = fh[c][K - 1];
+      else CARRY[par][c * 64 + col] = fh[c][K - 1];
     }
     __syncthreads();
-    if (lane == 0 && threadIdx.y == 0) {
+    T fl0[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      fl0[c] = g == 0 ? CARRY[par ^ 1][c * 64 + col] : XF[((g - 1) * 4 + c) * 64 + col];
+
+    // ---- finish the rows: Ly, output, wave speeds
+#pragma unroll
+    for (int m = 0; m < K; ++m) {
+      const int y = y0 + g * K + m;
+      const bool ok = y < ye && xin;
+      const int64_t gi = (int64_t)(ok ? y : ys) * nx + xc;
+      T o[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const T Ly = coef * (fh[c][m] - (m == 0 ? fl0[c] : fh[c][m - 1]));
+        o[c] = fma_t(cdt, Ly, Ureg[m][c]);
+        if (ok) __builtin_nontemporal_store(o[c], a.out + c * a.plane + gi);
+      }
+      if constexpr (SPEED) {
+        if (ok) {
+          double ax, ay;
+          wave_speeds_2d(double(o[0]), double(o[1]), double(o[2]), double(o[3]), gamma, ax, ay);
+          sxm = fmax(sxm, ax);
+          sym = fmax(sym, ay);
+        }
+      }
+    }
+  }
+  if constexpr (SPEED) {
+    sxm = wave_max(sxm);
+    sym = wave_max(sym);
+    if (col == 0) {
+      red[0][g] = sxm;
+      red[1][g] = sym;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
       double mx = red[0][0], my = red[1][0];
 #pragma unroll
-      for (int w = 1; w < NW; ++w) {
+      for (int w = 1; w < NG; ++w) {
         mx = fmax(mx, red[0][w]);
         my = fmax(my, red[1][w]);
       }
@@ -208,17 +308,32 @@ void col_kernel(ColArgs<T> a) {
   }
 }
 
-template <int KY, int R, int NW, typename T>
+template <int NG, int K, typename T>
 static int launch_col_t(ColArgs<T> a, hipStream_t s) {
-  constexpr int S = KY * R - 1;
-  a.nseg = (int)((a.ny + S - 1) / S);
+  constexpr int TY = ColTile<NG, K>::TY;
   const int64_t bx = (a.nx + 63) / 64;
-  const int64_t by = (a.nseg + NW - 1) / NW;
-  if (bx > 0x7fffffff || by > 65535) return set_error(WZN_ERR_SIZE, "grid too large (columns)");
-  hipLaunchKernelGGL((col_kernel<KY, R, NW, T>), dim3((unsigned)bx, (unsigned)by), dim3(64, NW), 0,
-                     s, a);
+  // about four workgroups per CU: split the rows into segments (multiples of TY rows)
+  int64_t nseg = (1024 + bx - 1) / bx;
+  const int64_t maxseg = (a.ny + TY - 1) / TY;
+  if (nseg > maxseg) nseg = maxseg;
+  if (nseg < 1) nseg = 1;
+  int64_t seg = (a.ny + nseg - 1) / nseg;
+  seg = (seg + TY - 1) / TY * TY;
+  nseg = (a.ny + seg - 1) / seg;
+  a.seg = (int)seg;
+  if (bx > 0x7fffffff || nseg > 65535) return set_error(WZN_ERR_SIZE, "grid too large (columns)");
+  if (a.speed_next_x)
+    hipLaunchKernelGGL((col_kernel<NG, K, T, true>), dim3((unsigned)bx, (unsigned)nseg),
+                       dim3(64 * NG), 0, s, a);
+  else
+    hipLaunchKernelGGL((col_kernel<NG, K, T, false>), dim3((unsigned)bx, (unsigned)nseg),
+                       dim3(64 * NG), 0, s, a);
   return check_launch("col_kernel");
 }
+
+// Column kernel shape: NG row groups of K rows.
+constexpr int COL_NG = 4;
+constexpr int COL_K = 2;
 
 // ------------------------------------------------------------------ host side
 template <typename T>
@@ -251,7 +366,15 @@ static ColArgs<T> col_args(const wzn_params* p, int64_t nx, int64_t ny, double d
   return a;
 }
 
-static Tuning1D tuning_2dx() { return Tuning1D{256, 4, ROW_LDS_TILE}; }
+// Launch shape of the x sweep (rows of 4 components): the process-wide row override when it
+// names a shape the 2D row kernel has, else 1024-cell tiles staged one sign at a time.
+static Tuning1D tuning_2dx() {
+  const Tuning1D o = row_override();
+  const bool ok = (o.layout == ROW_LDS_TILE && ((o.nt == 256 && (o.k == 4 || o.k == 2)) ||
+                                               (o.nt == 128 && o.k == 4))) ||
+                  (o.layout == ROW_LDS_SPLIT && o.nt == 256 && (o.k == 4 || o.k == 2));
+  return ok ? o : Tuning1D{256, 4, ROW_LDS_SPLIT};
+}
 
 template <typename T>
 int rhs_2d_t(const wzn_params* p, const T* u, T* dudt, int64_t nx, int64_t ny, double dx,
@@ -277,7 +400,7 @@ int rhs_2d_t(const wzn_params* p, const T* u, T* dudt, int64_t nx, int64_t ny, d
   ca.lx = dudt;
   ca.out = dudt;
   ca.mode = MODE_RHS;
-  return launch_col_t<4, 16, 4, T>(ca, s);
+  return launch_col_t<COL_NG, COL_K, T>(ca, s);
 }
 template int rhs_2d_t<double>(const wzn_params*, const double*, double*, int64_t, int64_t, double,
                               double, Workspace*, hipStream_t);
@@ -348,7 +471,7 @@ int rk3_run_2d_t(const wzn_params* p, T* u, T* stage, int64_t nx, int64_t ny, do
         ca.zero_x = &rx[old];
         ca.zero_y = &ry[old];
       }
-      st = launch_col_t<4, 16, 4, T>(ca, s);
+      st = launch_col_t<COL_NG, COL_K, T>(ca, s);
       if (st) return st;
     }
   }

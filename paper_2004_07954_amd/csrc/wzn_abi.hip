@@ -36,14 +36,16 @@ int launch_fill_double(double* p, double v, hipStream_t s) {
 
 static Tuning1D g_row_override = {0, 0, 0};
 
-// Launch shape of the 1D row kernel: the caller's override if set; otherwise 256-thread
-// workgroups (measured fastest at every size on MI355X) with the widest tile that still
-// leaves >= 256 workgroups (one per CU): k = 4 from 2^18 cells, k = 2 from 2^15, else 1.
+Tuning1D row_override() { return g_row_override; }
+
+// Launch shape of the 1D row kernel: the caller's override if set; otherwise, as measured on
+// MI355X, 1024-cell tiles with the signs staged one at a time from 3 * 2^18 cells (one round
+// of four workgroups per CU at 2^20 cells), 512-cell tiles from 2^15, else 256-cell tiles.
 Tuning1D tuning_1d(int nv, int64_t n) {
   if (nv == 1) return Tuning1D{64, 4, ROW_LDS_TILE};
   if (g_row_override.nt > 0) return g_row_override;
-  if (n >= (int64_t)256 * 4 * 256) return Tuning1D{256, 4, ROW_LDS_TILE};
-  if (n >= (int64_t)256 * 2 * 64) return Tuning1D{256, 2, ROW_LDS_TILE};
+  if (n >= (int64_t)3 << 18) return Tuning1D{256, 4, ROW_LDS_SPLIT};
+  if (n >= (int64_t)1 << 15) return Tuning1D{256, 2, ROW_LDS_TILE};
   return Tuning1D{256, 1, ROW_LDS_TILE};
 }
 
@@ -74,7 +76,8 @@ static int check_1d(const wzn_params* p, int64_t n, double dx, void* ws) {
   int st = check_params(p, false);
   if (st) return st;
   if (n < 6) return set_error(WZN_ERR_SIZE, "n = %lld < 6", (long long)n);
-  if (n > (int64_t)1 << 40) return set_error(WZN_ERR_SIZE, "n = %lld too large", (long long)n);
+  if (n > (int64_t)1 << 30)
+    return set_error(WZN_ERR_SIZE, "n = %lld > 2^30 cells per row", (long long)n);
   if (!(dx > 0.0)) return set_error(WZN_ERR_ARG, "dx must be positive");
   if (!ws) return set_error(WZN_ERR_ARG, "workspace is NULL");
   if (((uintptr_t)ws) & 255) return set_error(WZN_ERR_ARG, "workspace not 256-byte aligned");
@@ -155,6 +158,17 @@ int32_t wzn_set_row_tuning(int32_t nt, int32_t k, int32_t layout) {
     return set_error(WZN_ERR_ARG, "unsupported row tuning (nt=%d, k=%d, layout=%d)", nt, k,
                      layout);
   g_row_override = Tuning1D{nt, k, layout};
+  return WZN_OK;
+}
+
+int32_t wzn_get_row_tuning(int32_t nvar, int64_t n, int32_t* nt, int32_t* k, int32_t* layout) {
+  g_err[0] = 0;
+  if (!nt || !k || !layout) return set_error(WZN_ERR_ARG, "null output pointer");
+  if (nvar != 1 && nvar != 3) return set_error(WZN_ERR_ARG, "nvar must be 1 or 3");
+  const Tuning1D t = tuning_1d(nvar, n);
+  *nt = t.nt;
+  *k = t.k;
+  *layout = t.layout;
   return WZN_OK;
 }
 

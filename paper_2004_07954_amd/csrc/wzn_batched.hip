@@ -52,7 +52,8 @@ __global__ __launch_bounds__(NT) void batched_kernel(BatchArgs b) {
     const int inst = b.order ? b.order[qi] : qi;
     const int64_t off = b.offsets[inst];
     const int64_t n = b.offsets[inst + 1] - off;
-    if (n < 6 || off < 0 || off + n > b.total) continue;  // malformed instance: left untouched
+    // malformed instance (or one longer than a row may be): left untouched
+    if (n < 6 || n > ((int64_t)1 << 30) || off < 0 || off + n > b.total) continue;
     const double dx = b.dx[inst];
 
     RowArgs<double> a{};

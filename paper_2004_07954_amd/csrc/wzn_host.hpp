@@ -38,6 +38,7 @@ struct Tuning1D {
 };
 enum { ROW_LDS_TILE = 0, ROW_LDS_SPLIT = 1 };
 Tuning1D tuning_1d(int nv, int64_t n);
+Tuning1D row_override();  // the wzn_set_row_tuning override ({0, 0, 0} when unset)
 
 int set_error(int code, const char* fmt, ...);
 int check_launch(const char* what);

@@ -55,3 +55,33 @@ def test_host_only_calls():
     rc = L.wzn_rhs_1d(C.byref(p), C.c_void_p(256), C.c_void_p(512), 100, 0.1,
                       C.c_void_p(1000), None)
     assert rc == _lib.WZN_ERR_ARG  # unaligned workspace
+
+
+def test_row_tuning_host_calls():
+    """Launch-shape override: valid shapes are accepted and reported back, unknown ones are
+    rejected, (0, 0) restores the size-based choice; over-long rows are rejected."""
+    import ctypes as C
+    from paper_2004_07954_amd import _lib, autotune
+    from paper_2004_07954_amd._lib import WznError
+    try:
+        autotune.set_row_tuning(0, 0)
+        assert autotune.get_row_tuning(3, 1 << 20) == (256, 4, 1)
+        assert autotune.get_row_tuning(3, 65536) == (256, 2, 0)
+        assert autotune.get_row_tuning(3, 1000) == (256, 1, 0)
+        assert autotune.get_row_tuning(1, 200) == (64, 4, 0)
+        for shape in autotune.ROW_SHAPES:
+            autotune.set_row_tuning(*shape)
+            assert autotune.get_row_tuning(3, 12345) == shape
+        for shape in [(96, 4, 0), (256, 8, 1), (128, 8, 1), (64, 2, 1), (256, 4, 2)]:
+            with pytest.raises(WznError):
+                autotune.set_row_tuning(*shape)
+        with pytest.raises(WznError):
+            autotune.get_row_tuning(2, 100)
+    finally:
+        autotune.set_row_tuning(0, 0)
+    L = _lib.lib()
+    p = _lib.WznParams()
+    L.wzn_default_params(C.byref(p), _lib.WZN_EULER)
+    rc = L.wzn_rhs_1d(C.byref(p), C.c_void_p(256), C.c_void_p(512), (1 << 30) + 1, 0.1,
+                      C.c_void_p(1024), None)
+    assert rc == _lib.WZN_ERR_SIZE

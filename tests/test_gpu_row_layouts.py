@@ -72,11 +72,3 @@ def test_euler_shapes_agree(api, orc, n, bc):
             np.testing.assert_array_equal(g, ref_rhs, err_msg=str(shape))
             np.testing.assert_array_equal(ug, ref_run, err_msg=str(shape))
     autotune.set_row_tuning(0, 0)
-
-
-def test_row_tuning_rejects_unknown_shapes(api):
-    from paper_2004_07954_amd import autotune
-    from paper_2004_07954_amd._lib import WznError
-    for shape in [(96, 4, 0), (256, 8, 1), (128, 8, 1), (64, 2, 1), (256, 4, 2)]:
-        with pytest.raises(WznError):
-            autotune.set_row_tuning(*shape)
