@@ -81,8 +81,10 @@ __device__ __forceinline__ void flux_y(const T (&U)[4], T (&G)[4], T gm1) {
 // then w^- = w^+ - 2 alpha U in place).  The lower interface of a group's first row is the
 // last interface of the group below (LDS), of the previous iteration's last group (carried in
 // LDS), or at the segment's first row the boundary interface, reconstructed once per segment.
+// Four waves per SIMD (128 VGPRs; the fp64 variant with the wave-speed epilogue spills a few
+// bytes, which costs far less than dropping to three waves).
 template <int NG, int K, typename T, bool SPEED>
-__global__ __launch_bounds__(64 * NG)
+__global__ __launch_bounds__(64 * NG) __attribute__((amdgpu_waves_per_eu(4)))
 void col_kernel(ColArgs<T> a) {
   static_assert(NG >= 4, "the segment's boundary interface uses one group per component");
   using CT = ColTile<NG, K>;
@@ -331,9 +333,11 @@ static int launch_col_t(ColArgs<T> a, hipStream_t s) {
   return check_launch("col_kernel");
 }
 
-// Column kernel shape: NG row groups of K rows.
-constexpr int COL_NG = 4;
-constexpr int COL_K = 2;
+// Column kernel shape: NG row groups of K rows (K = 2 in fp64, 4 in fp32: the LDS of one
+// tile, 4 * (NG K + 6) * 64 elements, stays within 40 KB for four workgroups per CU).
+template <typename T> struct ColShape;
+template <> struct ColShape<double> { static constexpr int NG = 4, K = 2; };
+template <> struct ColShape<float> { static constexpr int NG = 4, K = 4; };
 
 // ------------------------------------------------------------------ host side
 template <typename T>
@@ -367,13 +371,14 @@ static ColArgs<T> col_args(const wzn_params* p, int64_t nx, int64_t ny, double d
 }
 
 // Launch shape of the x sweep (rows of 4 components): the process-wide row override when it
-// names a shape the 2D row kernel has, else 1024-cell tiles staged one sign at a time.
+// names a shape the 2D row kernel has, else 512-cell tiles with both signs staged (measured
+// fastest for 4096^2 in fp64 and fp32).
 static Tuning1D tuning_2dx() {
   const Tuning1D o = row_override();
   const bool ok = (o.layout == ROW_LDS_TILE && ((o.nt == 256 && (o.k == 4 || o.k == 2)) ||
                                                (o.nt == 128 && o.k == 4))) ||
                   (o.layout == ROW_LDS_SPLIT && o.nt == 256 && (o.k == 4 || o.k == 2));
-  return ok ? o : Tuning1D{256, 4, ROW_LDS_SPLIT};
+  return ok ? o : Tuning1D{256, 2, ROW_LDS_TILE};
 }
 
 template <typename T>
@@ -400,7 +405,7 @@ int rhs_2d_t(const wzn_params* p, const T* u, T* dudt, int64_t nx, int64_t ny, d
   ca.lx = dudt;
   ca.out = dudt;
   ca.mode = MODE_RHS;
-  return launch_col_t<COL_NG, COL_K, T>(ca, s);
+  return launch_col_t<ColShape<T>::NG, ColShape<T>::K, T>(ca, s);
 }
 template int rhs_2d_t<double>(const wzn_params*, const double*, double*, int64_t, int64_t, double,
                               double, Workspace*, hipStream_t);
@@ -471,7 +476,7 @@ int rk3_run_2d_t(const wzn_params* p, T* u, T* stage, int64_t nx, int64_t ny, do
         ca.zero_x = &rx[old];
         ca.zero_y = &ry[old];
       }
-      st = launch_col_t<COL_NG, COL_K, T>(ca, s);
+      st = launch_col_t<ColShape<T>::NG, ColShape<T>::K, T>(ca, s);
       if (st) return st;
     }
   }
