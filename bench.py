@@ -172,7 +172,8 @@ def bench_batched(steps, baseline_sample=48, use_graph=True):
     return {"workload": "batched_shock_tubes_B4096_seed4", "instances": int(len(lens)),
             "total_cells": int(cells), "steps": steps, "ms_batched": ms_batched,
             "value": cells * 3 * steps / (ms_batched * 1e-3), "unit": "cell-RHS/s",
-            "tuning": {"nt": tn.nt, "k": tn.k, "blocks_per_cu": tn.blocks_per_cu},
+            "tuning": {"nt": tn.nt, "k": tn.k, "blocks_per_cu": tn.blocks_per_cu,
+                       "layout": "split" if tn.layout == 1 else "tile"},
             "launch": "hip_graph" if graph is not None else "stream",
             "baseline_ms_estimate": ms_baseline, "baseline_sample": baseline_sample,
             "baseline_sample_ms": ms_sample,

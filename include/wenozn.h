@@ -171,14 +171,16 @@ int32_t wzn_rk3_step_2d(const wzn_params* p, void* u, void* stage, int64_t nx, i
  *   order    device int32 [batch]: the order in which instances are handed to workgroups
  *            (longest first balances the load), or NULL for 0 .. batch-1.
  *   tuning   host struct (NULL: defaults); nt in {64, 128, 256} threads per workgroup, k in
- *            {1, 2, 4} cells per thread (supported pairs: 64x2, 64x4, 128x2, 128x4, 256x1,
- *            256x2, 256x4); blocks_per_cu <= 0 takes the occupancy limit.
+ *            {1, 2, 4} cells per thread; layout WZN_ROW_LDS_TILE (pairs 64x2, 64x4, 128x2,
+ *            128x4, 256x1, 256x2, 256x4) or WZN_ROW_LDS_SPLIT (128x4, 256x2, 256x4), as for
+ *            wzn_set_row_tuning; blocks_per_cu <= 0 takes the occupancy limit.  Results do not
+ *            depend on the tuning (bit for bit).
  *   dt_out   NULL or device double [batch][nsteps] receiving every instance's dt history. */
 typedef struct {
   int32_t nt;
   int32_t k;
   int32_t blocks_per_cu;
-  int32_t reserved;
+  int32_t layout;
 } wzn_batch_tuning;
 
 int32_t wzn_batched_rk3_run_1d(const wzn_params* p, void* u, void* stage, int64_t total,

@@ -27,7 +27,7 @@ class WznParams(C.Structure):
 
 class WznBatchTuning(C.Structure):
     _fields_ = [("nt", C.c_int32), ("k", C.c_int32), ("blocks_per_cu", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("layout", C.c_int32)]
 
 
 # (name, restype, argtypes) of every symbol include/wenozn.h declares

@@ -191,8 +191,8 @@ def rk3_run_2d(u, dx, dy, nsteps, cfl=0.5, prm=None, dt=None, stage=None, record
     return dt_o
 
 
-def batch_tuning(nt=128, k=2, blocks_per_cu=0):
-    return _lib.WznBatchTuning(int(nt), int(k), int(blocks_per_cu), 0)
+def batch_tuning(nt=128, k=2, blocks_per_cu=0, layout=0):
+    return _lib.WznBatchTuning(int(nt), int(k), int(blocks_per_cu), int(layout))
 
 
 def lpt_order(lengths, device="cuda"):

@@ -11,8 +11,10 @@ import torch
 
 from . import api
 
-CANDIDATES = [(64, 2, 0), (64, 4, 0), (128, 2, 0), (128, 4, 0), (256, 1, 0), (256, 2, 0),
-              (256, 4, 0), (128, 2, 4), (64, 4, 8)]
+# (threads per workgroup, cells per thread, workgroups per CU (0: occupancy limit), layout)
+CANDIDATES = [(64, 2, 0, 0), (64, 4, 0, 0), (128, 2, 0, 0), (128, 4, 0, 0), (256, 1, 0, 0),
+              (256, 2, 0, 0), (256, 4, 0, 0), (128, 2, 4, 0), (64, 4, 8, 0), (128, 4, 0, 1),
+              (256, 2, 0, 1), (256, 4, 0, 1)]
 CACHE = os.environ.get("WZN_TUNING_CACHE",
                        os.path.join(os.path.expanduser("~"), ".cache", "wenozn", "tuning.json"))
 
@@ -21,7 +23,7 @@ def _key(u, batch):
     name = torch.cuda.get_device_name(u.device).replace(" ", "_")
     total = u.shape[1]
     bucket = 1 << max(0, int(total - 1).bit_length())  # next power of two
-    return "%s|batched|B%d|T%d" % (name, batch, bucket)
+    return "%s|batched2|B%d|T%d" % (name, batch, bucket)
 
 
 def _load():
@@ -50,13 +52,13 @@ def tune_batched(u, offsets, dx, order=None, probe_steps=3, candidates=CANDIDATE
     key = _key(u, batch)
     db = _load() if use_cache else {}
     if key in db:
-        nt, k, bpc = db[key]["choice"]
-        return api.batch_tuning(nt, k, bpc), db[key].get("ms", {})
+        nt, k, bpc, lay = db[key]["choice"]
+        return api.batch_tuning(nt, k, bpc, lay), db[key].get("ms", {})
     work = u.clone()
     stage = torch.empty((2,) + tuple(u.shape), dtype=u.dtype, device=u.device)
     timings = {}
-    for nt, k, bpc in candidates:
-        tn = api.batch_tuning(nt, k, bpc)
+    for nt, k, bpc, lay in candidates:
+        tn = api.batch_tuning(nt, k, bpc, lay)
         work.copy_(u)
         api.batched_rk3_run_1d(work, offsets, dx, 1, order=order, tuning=tn, stage=stage)
         work.copy_(u)
@@ -67,19 +69,18 @@ def tune_batched(u, offsets, dx, order=None, probe_steps=3, candidates=CANDIDATE
                                stage=stage)
         e.record()
         torch.cuda.synchronize()
-        timings["%d/%d/%d" % (nt, k, bpc)] = s.elapsed_time(e) / probe_steps
+        key_t = "%d/%d/%d/%d" % (nt, k, bpc, lay)
+        timings[key_t] = s.elapsed_time(e) / probe_steps
         if log:
-            log("tune nt=%d k=%d bpc=%d: %.3f ms/step" % (nt, k, bpc, timings["%d/%d/%d" % (nt, k, bpc)]))
+            log("tune nt=%d k=%d bpc=%d layout=%d: %.3f ms/step" % (nt, k, bpc, lay, timings[key_t]))
     best = min(timings, key=timings.get)
-    nt, k, bpc = (int(x) for x in best.split("/"))
+    nt, k, bpc, lay = (int(x) for x in best.split("/"))
     if use_cache:
-        db[key] = {"choice": [nt, k, bpc], "ms": timings}
+        db[key] = {"choice": [nt, k, bpc, lay], "ms": timings}
         _store(db)
-    return api.batch_tuning(nt, k, bpc), timings
+    return api.batch_tuning(nt, k, bpc, lay), timings
 
 
-# (threads per workgroup, cells per thread, layout): layout 0 stages both signs of the split
-# flux of a workgroup tile in LDS, layout 1 stages one sign at a time (half the LDS).
 ROW_SHAPES = [(256, 4, 0), (256, 2, 0), (256, 1, 0), (128, 4, 0), (128, 8, 0), (64, 8, 0),
               (64, 4, 0), (64, 2, 0), (64, 1, 0), (256, 4, 1), (256, 2, 1), (128, 4, 1), (64, 4, 1)]
 

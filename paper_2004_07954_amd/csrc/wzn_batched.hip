@@ -33,7 +33,7 @@ struct BatchArgs {
   double* dt_out;           // [batch][nsteps] or null
 };
 
-template <int NT, int K>
+template <int NT, int K, bool SPLIT>
 __global__ __launch_bounds__(NT) void batched_kernel(BatchArgs b) {
   constexpr int TT = NT * K;
   extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -86,19 +86,19 @@ __global__ __launch_bounds__(NT) void batched_kernel(BatchArgs b) {
         a.rk_b = k == 0 ? 1.0 : (k == 1 ? 1.0 / 4.0 : 2.0 / 3.0);
         smax = 0.0;
         for (int64_t t = 0; t < ntiles; ++t)
-          row_tile<NT, K, SYS_EULER1, double, true>(a, t * TT, off, alpha, dt, W, EX, smax);
+          row_tile<NT, K, SYS_EULER1, double, true, SPLIT>(a, t * TT, off, alpha, dt, W, EX, smax);
         alpha = block_max<NT>(smax, red);  // alpha of the next stage's input
       }
     }
   }
 }
 
-template <int NT, int K>
+template <int NT, int K, bool SPLIT>
 static int launch_batched_t(const BatchArgs& b, int blocks_per_cu, hipStream_t s) {
-  const size_t lds = tile_lds_bytes<NT, K, SYS_EULER1, double>();
+  const size_t lds = tile_lds_bytes<NT, K, SYS_EULER1, double, SPLIT>();
   static bool attr_set = false;
   if (!attr_set) {
-    if (hipFuncSetAttribute((const void*)batched_kernel<NT, K>,
+    if (hipFuncSetAttribute((const void*)batched_kernel<NT, K, SPLIT>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
       return set_error(WZN_ERR_HIP, "hipFuncSetAttribute(batched_kernel) failed");
     attr_set = true;
@@ -107,14 +107,14 @@ static int launch_batched_t(const BatchArgs& b, int blocks_per_cu, hipStream_t s
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return set_error(WZN_ERR_HIP, "cannot query the device");
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)batched_kernel<NT, K>, NT,
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)batched_kernel<NT, K, SPLIT>, NT,
                                                    lds) != hipSuccess || occ < 1)
     occ = 1;
   int per_cu = blocks_per_cu > 0 ? (blocks_per_cu < occ ? blocks_per_cu : occ) : occ;
   int64_t grid = (int64_t)cus * per_cu;
   if (grid > b.batch) grid = b.batch;
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL((batched_kernel<NT, K>), dim3((unsigned)grid), dim3(NT), lds, s, b);
+  hipLaunchKernelGGL((batched_kernel<NT, K, SPLIT>), dim3((unsigned)grid), dim3(NT), lds, s, b);
   return check_launch("batched_kernel");
 }
 
@@ -142,14 +142,22 @@ int batched_rk3_run_1d(const wzn_params* p, double* u, double* stage, int64_t to
   int st = launch_zero_words(ws->counter, 1, s);
   if (st) return st;
   const int nt = tn ? tn->nt : 128, k = tn ? tn->k : 2, bpc = tn ? tn->blocks_per_cu : 0;
-  if (nt == 64 && k == 4) return launch_batched_t<64, 4>(b, bpc, s);
-  if (nt == 64 && k == 2) return launch_batched_t<64, 2>(b, bpc, s);
-  if (nt == 128 && k == 2) return launch_batched_t<128, 2>(b, bpc, s);
-  if (nt == 128 && k == 4) return launch_batched_t<128, 4>(b, bpc, s);
-  if (nt == 256 && k == 1) return launch_batched_t<256, 1>(b, bpc, s);
-  if (nt == 256 && k == 2) return launch_batched_t<256, 2>(b, bpc, s);
-  if (nt == 256 && k == 4) return launch_batched_t<256, 4>(b, bpc, s);
-  return set_error(WZN_ERR_ARG, "unsupported batched tuning (nt=%d, k=%d)", nt, k);
+  const int lay = tn ? tn->layout : ROW_LDS_TILE;
+  if (lay == ROW_LDS_TILE) {
+    if (nt == 64 && k == 4) return launch_batched_t<64, 4, false>(b, bpc, s);
+    if (nt == 64 && k == 2) return launch_batched_t<64, 2, false>(b, bpc, s);
+    if (nt == 128 && k == 2) return launch_batched_t<128, 2, false>(b, bpc, s);
+    if (nt == 128 && k == 4) return launch_batched_t<128, 4, false>(b, bpc, s);
+    if (nt == 256 && k == 1) return launch_batched_t<256, 1, false>(b, bpc, s);
+    if (nt == 256 && k == 2) return launch_batched_t<256, 2, false>(b, bpc, s);
+    if (nt == 256 && k == 4) return launch_batched_t<256, 4, false>(b, bpc, s);
+  } else if (lay == ROW_LDS_SPLIT) {
+    if (nt == 128 && k == 4) return launch_batched_t<128, 4, true>(b, bpc, s);
+    if (nt == 256 && k == 2) return launch_batched_t<256, 2, true>(b, bpc, s);
+    if (nt == 256 && k == 4) return launch_batched_t<256, 4, true>(b, bpc, s);
+  }
+  return set_error(WZN_ERR_ARG, "unsupported batched tuning (nt=%d, k=%d, layout=%d)", nt, k,
+                   lay);
 }
 
 }  // namespace wzn

@@ -56,16 +56,17 @@ def make_batch(lens, seed):
 LENS = [6, 7, 100, 255, 256, 257, 511, 1024, 1025, 3000, 40, 777]
 
 
-@pytest.mark.parametrize("nt,k", [(64, 2), (64, 4), (128, 2), (128, 4), (256, 1), (256, 2),
-                                  (256, 4)])
-def test_batched_matches_single_and_oracle(api, orc, nt, k):
+@pytest.mark.parametrize("nt,k,lay", [(64, 2, 0), (64, 4, 0), (128, 2, 0), (128, 4, 0), (256, 1, 0),
+                                      (256, 2, 0), (256, 4, 0), (128, 4, 1), (256, 2, 1),
+                                      (256, 4, 1)])
+def test_batched_matches_single_and_oracle(api, orc, nt, k, lay):
     import torch
-    note("batched vs single vs oracle", nt, k)
+    note("batched vs single vs oracle", nt, k, lay)
     U, offs, dx, Ug, offg, dxg = make_batch(LENS, seed=41)
     nsteps = 12
     order = api.lpt_order(np.diff(offs))
     dtb = api.batched_rk3_run_1d(Ug, offg, dxg, nsteps, order=order,
-                                 tuning=api.batch_tuning(nt, k), record=True)
+                                 tuning=api.batch_tuning(nt, k, 0, lay), record=True)
     torch.cuda.synchronize()
     Ub = Ug.cpu().numpy()
     dtb = dtb.cpu().numpy()
@@ -137,5 +138,7 @@ def test_batched_bad_arguments(api):
     U, offs, dx, Ug, offg, dxg = make_batch([10, 20], seed=1)
     with pytest.raises(WznError):
         api.batched_rk3_run_1d(Ug, offg, dxg, 2, tuning=api.batch_tuning(96, 2))
+    with pytest.raises(WznError):
+        api.batched_rk3_run_1d(Ug, offg, dxg, 2, tuning=api.batch_tuning(64, 2, 0, 1))
     with pytest.raises(WznError):
         api.batched_rk3_run_1d(Ug, offg, dxg, 2, prm=api.params("euler", lf_alpha=1.0))
