@@ -300,6 +300,18 @@ __device__ __forceinline__ void row_tile(const RowArgs<T>& a, int64_t g0l, int64
       }
     }
     __syncthreads();
+    if (SPLIT && ph == 0 && a.mode == MODE_STAGE && a.un) {
+      // warm the caches with this thread's U^n lines, read in the second phase: direct-to-LDS
+      // loads into a scratch area that is never read, so no registers are held while the
+      // first phase's windows run
+      __shared__ int PF[NT];
+      const int cc = c0 < n ? c0 : n - 1;
+#pragma unroll
+      for (int c = 0; c < NV; ++c)
+        __builtin_amdgcn_global_load_lds(
+            (const void*)(a.un + c * a.plane + rowoff + cc),
+            (__attribute__((address_space(3))) void*)(PF + wave * 64), 4, 0, 0);
+    }
 
     // ---- left boundary interface of the tile: one (component, sign) per lane
     if (tid < NS * NV) {
