@@ -65,6 +65,10 @@ def lib():
                                      C.POINTER(OrcParams), d, p]
         L.orc_rk3_run_2d_f64.argtypes = [i32, i32, i64, i64, p, d, d, d, C.c_int32, p,
                                          C.POINTER(OrcParams), d, p]
+        L.orc_rhs_1d_char_f64.argtypes = [i32, i64, p, p, d, p, C.POINTER(OrcParams), d, p]
+        L.orc_roe_eigen_f64.argtypes = [p, p, d, p, p]
+        L.orc_rk3_run_1d_char_f64.argtypes = [i32, i64, p, d, d, C.c_int32,
+                                              C.POINTER(OrcParams), d, p, p]
         L.orc_num_threads.restype = C.c_int
         _LIB = L
     return _LIB
@@ -196,6 +200,40 @@ def rk3_run_2d(u, dx, dy, nsteps, cfl=0.5, dt=None, bcx=BC_TRANSMISSIVE, bcy=BC_
     lib().orc_rk3_run_2d_f64(bcx, bcy, nx, ny, _ptr(u), dx, dy, cfl, nsteps, _ptr(dt),
                              C.byref(prm), gamma, _ptr(dt_out))
     return u, dt_out
+
+
+def rhs_1d_char(u, dx, bc=BC_TRANSMISSIVE, alpha3=None, prm=None, gamma=GAMMA):
+    """L(U) of 1D Euler with the reconstruction in local characteristic fields; returns
+    (L, alpha3_used) with the three per-field LF alphas."""
+    prm = prm or params()
+    u = _f64(u)
+    n = u.shape[-1]
+    out = np.zeros_like(u)
+    a_in = None if alpha3 is None else _f64(alpha3)
+    a_out = np.zeros(3)
+    lib().orc_rhs_1d_char_f64(bc, n, _ptr(u), _ptr(out), dx, _ptr(a_in), C.byref(prm), gamma,
+                              _ptr(a_out))
+    return out, a_out
+
+
+def roe_eigen(UL, UR, gamma=GAMMA):
+    """(R, Lc) at the Roe average of two states (3x3 arrays)."""
+    R, Lc = np.zeros(9), np.zeros(9)
+    lib().orc_roe_eigen_f64(_ptr(_f64(UL)), _ptr(_f64(UR)), gamma, _ptr(R), _ptr(Lc))
+    return R.reshape(3, 3), Lc.reshape(3, 3)
+
+
+def rk3_run_1d_char(u, dx, nsteps, cfl=0.5, bc=BC_TRANSMISSIVE, prm=None, gamma=GAMMA):
+    """nsteps TVD-RK3 steps of the characteristic scheme; returns (u, dt[nsteps],
+    alpha[nsteps, 3 stages, 3 fields])."""
+    prm = prm or params()
+    u = _f64(u).copy()
+    n = u.shape[-1]
+    dt_out = np.zeros(nsteps)
+    al_out = np.zeros(nsteps * 9)
+    lib().orc_rk3_run_1d_char_f64(bc, n, _ptr(u), dx, cfl, nsteps, C.byref(prm), gamma,
+                                  _ptr(dt_out), _ptr(al_out))
+    return u, dt_out, al_out.reshape(nsteps, 3, 3)
 
 
 def num_threads():

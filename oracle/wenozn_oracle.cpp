@@ -245,6 +245,114 @@ static void rhs_1d(int sys, int bc, int64_t n, const T* u, T* dudt, T dx, double
       dudt[v * n + i] = -(fh[v * (n + 1) + i + 1] - fh[v * (n + 1) + i]) / dx;
 }
 
+// ---------------------------------------------------------------- 1D Euler, local characteristic fields
+// Sec. 4.3: Lax-Friedrichs splitting with the WENO reconstruction carried out in local
+// characteristic fields (the procedure of the scheme family the paper cites there).  The paper
+// gives no further detail; the readings taken are:
+//   * the state at x_{i+1/2} is the Roe average of U_i and U_{i+1}
+//     (u, H = (E + p)/rho weighted by sqrt(rho); c^2 = (gamma - 1)(H - u^2/2));
+//   * R has the right eigenvectors of the flux Jacobian there as columns,
+//     (1, u - c, H - u c), (1, u, u^2/2), (1, u + c, H + u c), and Lc = R^{-1};
+//   * the split is made field by field: g+-_j = (Lc F_j +- alpha_k Lc U_j)/2 over the stencil
+//     cells, alpha_k = max over interior cells of |lambda_k(U_j)|, lambda = (u - c, u, u + c),
+//     recomputed per RHS evaluation;
+//   * ghat_k = WZN(g+_{i-2..i+2}) + WZN(g-_{i+3..i-1}) (mirrored), fhat = R ghat.
+static inline double sqrtv(double x) { return std::sqrt(x); }
+
+template <class T>
+static void roe_eigen(const T* UL, const T* UR, const Phys& ph, T R[3][3], T Lc[3][3]) {
+  const T g = T(ph.gamma);
+  const T uL = UL[1] / UL[0], uR = UR[1] / UR[0];
+  const T pL = (g - T(1)) * (UL[2] - T(1) / T(2) * UL[0] * uL * uL);
+  const T pR = (g - T(1)) * (UR[2] - T(1) / T(2) * UR[0] * uR * uR);
+  const T HL = (UL[2] + pL) / UL[0], HR = (UR[2] + pR) / UR[0];
+  const T sL = sqrtv(UL[0]), sR = sqrtv(UR[0]);
+  const T u = (sL * uL + sR * uR) / (sL + sR);
+  const T H = (sL * HL + sR * HR) / (sL + sR);
+  const T c = sqrtv((g - T(1)) * (H - T(1) / T(2) * u * u));
+  R[0][0] = T(1);          R[0][1] = T(1);                R[0][2] = T(1);
+  R[1][0] = u - c;         R[1][1] = u;                   R[1][2] = u + c;
+  R[2][0] = H - u * c;     R[2][1] = T(1) / T(2) * u * u; R[2][2] = H + u * c;
+  const T b1 = (g - T(1)) / (c * c);
+  const T b2 = T(1) / T(2) * u * u * b1;
+  Lc[0][0] = T(1) / T(2) * (b2 + u / c);
+  Lc[0][1] = -T(1) / T(2) * (b1 * u + T(1) / c);
+  Lc[0][2] = T(1) / T(2) * b1;
+  Lc[1][0] = T(1) - b2;
+  Lc[1][1] = b1 * u;
+  Lc[1][2] = -b1;
+  Lc[2][0] = T(1) / T(2) * (b2 - u / c);
+  Lc[2][1] = -T(1) / T(2) * (b1 * u - T(1) / c);
+  Lc[2][2] = T(1) / T(2) * b1;
+}
+
+// Per-field global LF alphas: max over interior cells of |u - c|, |u|, |u + c|.
+static void lf_alpha_char(int64_t n, const double* u, const Phys& ph, double* a3) {
+  double m0 = 0.0, m1 = 0.0, m2 = 0.0;
+#pragma omp parallel for reduction(max : m0, m1, m2)
+  for (int64_t i = 0; i < n; ++i) {
+    const double rho = u[i], m = u[n + i], E = u[2 * n + i];
+    const double v = m / rho;
+    const double p = (ph.gamma - 1.0) * (E - 0.5 * rho * v * v);
+    const double c = std::sqrt(ph.gamma * p / rho);
+    m0 = std::max(m0, std::fabs(v - c));
+    m1 = std::max(m1, std::fabs(v));
+    m2 = std::max(m2, std::fabs(v + c));
+  }
+  a3[0] = m0; a3[1] = m1; a3[2] = m2;
+}
+
+template <class T>
+static void rhs_1d_char(int bc, int64_t n, const T* u, T* dudt, T dx, const double* a3,
+                        const OrcParams& P, const Phys& ph) {
+  const int64_t np = n + 6;  // padded: cell i lives at i + 3
+  std::vector<T> Up(3 * np), Fp(3 * np), fh(3 * (n + 1));
+  for (int v = 0; v < 3; ++v)
+    for (int64_t g = -3; g < n + 3; ++g) Up[v * np + g + 3] = u[v * n + ghost_index(g, n, bc)];
+  for (int64_t j = 0; j < np; ++j) {
+    T U[3] = {Up[j], Up[np + j], Up[2 * np + j]}, F[3];
+    euler1_flux(U, F, ph);
+    for (int v = 0; v < 3; ++v) Fp[v * np + j] = F[v];
+  }
+#pragma omp parallel for
+  for (int64_t k = 0; k <= n; ++k) {
+    const int64_t i = k - 1 + 3;  // padded index of cell i; interface x_{i+1/2}
+    T UL[3] = {Up[i], Up[np + i], Up[2 * np + i]};
+    T UR[3] = {Up[i + 1], Up[np + i + 1], Up[2 * np + i + 1]};
+    T R[3][3], Lc[3][3];
+    roe_eigen(UL, UR, ph, R, Lc);
+    // characteristic split fluxes over the cells i-2 .. i+3
+    T gp[3][6], gm[3][6];
+    for (int j = 0; j < 6; ++j) {
+      const int64_t cj = i - 2 + j;
+      for (int f = 0; f < 3; ++f) {
+        T V = T(0), G = T(0);
+        for (int v = 0; v < 3; ++v) {
+          V = V + Lc[f][v] * Up[v * np + cj];
+          G = G + Lc[f][v] * Fp[v * np + cj];
+        }
+        gp[f][j] = T(1) / T(2) * (G + T(a3[f]) * V);
+        gm[f][j] = T(1) / T(2) * (G - T(a3[f]) * V);
+      }
+    }
+    T gh[3];
+    for (int f = 0; f < 3; ++f) {
+      // positions 0..5 <-> cells i-2 .. i+3
+      T hp = reconstruct(gp[f][0], gp[f][1], gp[f][2], gp[f][3], gp[f][4], P).fhat;
+      T hm = reconstruct(gm[f][5], gm[f][4], gm[f][3], gm[f][2], gm[f][1], P).fhat;
+      gh[f] = hp + hm;
+    }
+    for (int v = 0; v < 3; ++v) {
+      T s = T(0);
+      for (int f = 0; f < 3; ++f) s = s + R[v][f] * gh[f];
+      fh[v * (n + 1) + k] = s;
+    }
+  }
+  for (int v = 0; v < 3; ++v)
+    for (int64_t i = 0; i < n; ++i)
+      dudt[v * n + i] = -(fh[v * (n + 1) + i + 1] - fh[v * (n + 1) + i]) / dx;
+}
+
 // ---------------------------------------------------------------- 2D right-hand side
 // Dimension by dimension (Sec. 4.4, eq:2d): L = -(Fhat_{i+1/2,j} - Fhat_{i-1/2,j})/dx
 // - (Ghat_{i,j+1/2} - Ghat_{i,j-1/2})/dy, each a 1D WENO-ZN reconstruction of the
@@ -511,6 +619,56 @@ void orc_rk3_run_2d_f64(int bcx, int bcy, int64_t nx, int64_t ny, double* u, dou
       rhs_2d<double>(bcx, bcy, nx, ny, us.data(), L.data(), dx, dy, ax, ay, *P, ph);
       for (int64_t k = 0; k < M; ++k)
         us[k] = RK_A[s] * un[k] + RK_B[s] * (us[k] + dt * L[k]);
+    }
+    std::memcpy(u, us.data(), sizeof(double) * M);
+    if (dt_out) dt_out[st] = dt;
+  }
+}
+
+// ---- 1D Euler in local characteristic fields (fp64).  alpha3_in: NULL -> the per-field
+// global alphas of u; otherwise the three frozen alphas.  alpha3_out (may be NULL) receives the
+// alphas used.
+void orc_rhs_1d_char_f64(int bc, int64_t n, const double* u, double* dudt, double dx,
+                         const double* alpha3_in, const OrcParams* P, double gamma,
+                         double* alpha3_out) {
+  Phys ph{0.0, gamma};
+  double a3[3];
+  if (alpha3_in) { a3[0] = alpha3_in[0]; a3[1] = alpha3_in[1]; a3[2] = alpha3_in[2]; }
+  else lf_alpha_char(n, u, ph, a3);
+  rhs_1d_char<double>(bc, n, u, dudt, dx, a3, *P, ph);
+  if (alpha3_out) for (int f = 0; f < 3; ++f) alpha3_out[f] = a3[f];
+}
+
+// The eigenvector matrices at the Roe average of two states (row-major R then Lc).
+void orc_roe_eigen_f64(const double* UL, const double* UR, double gamma, double* R9,
+                       double* L9) {
+  Phys ph{0.0, gamma};
+  double R[3][3], Lc[3][3];
+  roe_eigen(UL, UR, ph, R, Lc);
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) { R9[3 * r + c] = R[r][c]; L9[3 * r + c] = Lc[r][c]; }
+}
+
+// ---- nsteps TVD-RK3 steps of the characteristic scheme, in place.  dt from U^n as
+// cfl dx / max(|u| + c) (Sec. 4.3); per-field alphas recomputed for every stage.
+// dt_out [nsteps] and alpha_out [nsteps][3 stages][3 fields] may be NULL.
+void orc_rk3_run_1d_char_f64(int bc, int64_t n, double* u, double dx, double cfl,
+                             int32_t nsteps, const OrcParams* P, double gamma, double* dt_out,
+                             double* alpha_out) {
+  Phys ph{0.0, gamma};
+  const int64_t M = 3 * n;
+  std::vector<double> un(M), us(M), L(M);
+  for (int32_t st = 0; st < nsteps; ++st) {
+    std::memcpy(un.data(), u, sizeof(double) * M);
+    std::memcpy(us.data(), u, sizeof(double) * M);
+    const double dt = cfl * dx / lf_alpha_1d(SYS_EULER1, n, u, ph);
+    for (int s = 0; s < 3; ++s) {
+      double a3[3];
+      lf_alpha_char(n, us.data(), ph, a3);
+      rhs_1d_char<double>(bc, n, us.data(), L.data(), dx, a3, *P, ph);
+      for (int64_t k = 0; k < M; ++k)
+        us[k] = RK_A[s] * un[k] + RK_B[s] * (us[k] + dt * L[k]);
+      if (alpha_out) for (int f = 0; f < 3; ++f) alpha_out[9 * st + 3 * s + f] = a3[f];
     }
     std::memcpy(u, us.data(), sizeof(double) * M);
     if (dt_out) dt_out[st] = dt;
