@@ -27,18 +27,26 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash():
+# Sources each profiled kernel is built from: a committed counter profile is used only while
+# the hash of these files is the one it was taken on.
+ROW_KERNEL_SOURCES = ("wzn_rows.hip", "wzn_rows.hpp", "wzn_tile.hpp", "wzn_device.hpp",
+                      "wzn_1d.hip", "wzn_host.hpp")
+CHAR_KERNEL_SOURCES = ("wzn_char.hip", "wzn_rows.hpp", "wzn_tile.hpp", "wzn_device.hpp",
+                       "wzn_host.hpp")
+
+
+def kernel_source_hash(files):
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2004_07954_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".hpp")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
+    for f in sorted(files):
+        h.update(f.encode())
+        h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 
-def committed_profile(kind, kernel, workload, key):
+def committed_profile(kind, kernel, workload, key, sources):
     """A figure from a committed rocprofv3 --pmc summary (profiles/<kind>_<kernel>_<workload>.md,
-    line '<KIND>_JSON {...}'), if it was taken on the current kernel sources (else None)."""
+    line '<KIND>_JSON {...}'), if it was taken on the kernel's current sources (else None)."""
     path = os.path.join(ROOT, "profiles", "%s_%s_%s.md" % (kind, kernel, workload))
     if not os.path.exists(path):
         return None
@@ -47,7 +55,7 @@ def committed_profile(kind, kernel, workload, key):
     for line in open(path):
         if line.startswith(tag):
             rec = json.loads(line[len(tag):])
-    if rec is None or rec.get("source_hash") != kernel_source_hash():
+    if rec is None or rec.get("source_hash") != kernel_source_hash(sources):
         return None
     return rec.get(key)
 
@@ -181,6 +189,57 @@ def bench_batched(steps, baseline_sample=48, use_graph=True):
             "nonfinite_instances": bad_inst}
 
 
+def bench_char(n, steps, warmup=3, cpu_steps=3):
+    """Secondary figure: the paper's own 1D Euler setup (Sec. 4.3), WENO-ZN in local
+    characteristic fields with per-field Lax-Friedrichs alphas, same data, grid and CFL as the
+    headline workload.  The stage kernel is fp64-VALU bound: the roofline reports its
+    measured VALU instructions per interface (committed counter profile) against the issue
+    peak.  The oracle's characteristic run on the same grid is timed beside it."""
+    import torch
+    from paper_2004_07954_amd import api, inputs as I
+    u0, dx = I.shu_osher_like(n)
+    base = torch.tensor(u0, dtype=torch.float64, device="cuda")
+    u = base.clone()
+    stage = torch.empty((2, 3, n), dtype=torch.float64, device="cuda")
+    api.rk3_run_1d_char(u, dx, warmup, cfl=0.5, stage=stage)
+    u.copy_(base)
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    api.rk3_run_1d_char(u, dx, steps, cfl=0.5, stage=stage)
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e)
+    assert torch.isfinite(u).all().item() and u[0].min().item() > 0
+    kernel_ms = ms / (3 * steps)
+    workload = "euler1d_n%d" % n
+    valu = committed_profile("valu", "char_kernel_256", workload, "valu_instr_per_cell",
+                             CHAR_KERNEL_SOURCES)
+    traffic = committed_profile("traffic", "char_kernel_256", workload, "hbm_bytes_per_launch",
+                                CHAR_KERNEL_SOURCES)
+    rec = {"workload": "euler1d_shu_osher_like_characteristic", "n_cells": n, "steps": steps,
+           "ms_per_step": ms / steps, "value": n * 3 * steps / (ms * 1e-3),
+           "unit": "cell-RHS/s", "kernel": "char_kernel<256, field-outer>",
+           "kernel_ms": kernel_ms,
+           "hbm_gbs_algorithmic": n * (48 + 72 + 72) / 3.0 / (kernel_ms * 1e-3) / 1e9,
+           "hbm_bytes_per_launch_measured": traffic,
+           "roofline": {"bound": "alu", "unit": "VALU lane-instr/s",
+                        "valu_instr_per_cell_stage": valu,
+                        "achieved": valu * n / (kernel_ms * 1e-3) if valu else None,
+                        "peak": VALU_LANE_PEAK,
+                        "frac": valu * n / (kernel_ms * 1e-3) / VALU_LANE_PEAK if valu else None}}
+    if cpu_steps:
+        from oracle import binding as orc
+        t0 = time.perf_counter()
+        orc.rk3_run_1d_char(u0, dx, cpu_steps, cfl=0.5)
+        el = time.perf_counter() - t0
+        rec["cpu_baseline"] = {"value": n * 3 * cpu_steps / el, "unit": "cell-RHS/s",
+                               "cores": orc.num_threads(), "kind": "oracle",
+                               "sample": "%d characteristic TVD-RK3 steps at N=%d, %.1f s"
+                                         % (cpu_steps, n, el)}
+    return rec
+
+
 def bench_adjoint(n=65536, nsteps=400, ckpt=20, reps=3):
     """Secondary figure: the discrete adjoint of a periodic 1D Euler run (N = 65536, 400 steps,
     checkpoints every 20; loss 1/2 ||rho_T - rho_target||^2).  Reports the forward time (run
@@ -227,6 +286,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--steps-batched", type=int, default=500)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-char", action="store_true",
+                    help="skip the characteristic-field secondary figure")
+    ap.add_argument("--steps-char", type=int, default=300)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed region, copy 256 MiB with a plain torch copy "
                          "(reference kernel for rocprof FETCH_SIZE / WRITE_SIZE scaling)")
@@ -298,8 +360,9 @@ def main():
     kname = "row_kernel<%d, %d, EULER1, double, %s>" % (nt, kk, "split" if lay == 1 else "tile")
     workload = "euler1d_n%d" % n
     ktag = "row_kernel_%dx%d_%s" % (nt, kk, "split" if lay == 1 else "tile")
-    traffic = committed_profile("traffic", ktag, workload, "hbm_bytes_per_launch")
-    valu = committed_profile("valu", ktag, workload, "valu_instr_per_cell")
+    traffic = committed_profile("traffic", ktag, workload, "hbm_bytes_per_launch",
+                                ROW_KERNEL_SOURCES)
+    valu = committed_profile("valu", ktag, workload, "valu_instr_per_cell", ROW_KERNEL_SOURCES)
     flops = FLOPS_PER_CELL_STAGE * n / (kernel_ms * 1e-3) / 1e12
     rec = {
         "metric": "WENO-ZN RHS cell-updates/s (1D Euler, fused TVD-RK3 stages)",
@@ -351,6 +414,10 @@ def main():
         log("adjoint: N=65536, 400 steps")
         rec.setdefault("secondary", {})["adjoint"] = bench_adjoint()
         rec["adjoint_fwd_ratio"] = rec["secondary"]["adjoint"]["adjoint_fwd_ratio"]
+    if not args.no_char:
+        log("characteristic fields, N =", n)
+        rec.setdefault("secondary", {})["characteristic"] = bench_char(
+            n, args.steps_char, cpu_steps=0 if args.no_cpu_baseline else 3)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         rec["cpu_baseline"] = cpu_baseline(n)

@@ -128,6 +128,34 @@ int32_t wzn_rk3_step_1d(const wzn_params* p, void* u, void* stage, int64_t n, do
                         double cfl, const double* dt_in, double* dt_out, void* ws,
                         void* stream);
 
+/* ---------------------------------------------------------------- 1D Euler, characteristic fields
+ * The paper's 1D Euler setup (Sec. 4.3): the Lax-Friedrichs split and the WENO-ZN
+ * reconstruction are carried out in local characteristic fields.  For the interface x_{i+1/2}
+ * the flux Jacobian is diagonalised at the Roe average of U_i and U_{i+1}: R has the right
+ * eigenvectors (1, u - c, H - u c), (1, u, u^2/2), (1, u + c, H + u c) as columns and
+ * Lc = R^{-1}; the cells i-2 .. i+3 are projected with that Lc, field k is split with its own
+ * global alpha_k = max over cells of |lambda_k|, lambda = (u - c, u, u + c), reconstructed as
+ * in wzn_rhs_1d, and Fhat = R ghat.  Requires p->system == WZN_EULER, fp64.
+ *
+ * wzn_rhs_1d_char: dudt = L(u) for u[3][n]; u and dudt must not alias.
+ *   alpha3  NULL: the three alphas are p->lf_alpha_x (all three) if >= 0, else reduced from u;
+ *           else a device array [3] of per-field alphas used as given. */
+int32_t wzn_rhs_1d_char(const wzn_params* p, const void* u, void* dudt, int64_t n, double dx,
+                        const double* alpha3, void* ws, void* stream);
+
+/* wzn_rk3_run_1d_char: advance u[3][n] in place by `nsteps` TVD-RK3 steps of the
+ * characteristic scheme; the arguments are those of wzn_rk3_run_1d except that the alphas
+ * come in triples:
+ *   alpha_in  NULL (reduced per stage from each stage input, or p->lf_alpha_x for all if >= 0)
+ *             or a device array [nsteps][3 stages][3 fields] of frozen alphas;
+ *   alpha_out NULL or a device array [nsteps][3][3] receiving them;
+ *   dt = cfl dx / max(|u| + c) of U^n unless dt_in is given.
+ * Enqueued as 2 + 3 * nsteps kernels with no host synchronisation. */
+int32_t wzn_rk3_run_1d_char(const wzn_params* p, void* u, void* stage, int64_t n, double dx,
+                            double cfl, int32_t nsteps, const double* dt_in,
+                            const double* alpha_in, double* dt_out, double* alpha_out, void* ws,
+                            void* stream);
+
 /* ---------------------------------------------------------------- 2D (Euler, Sec. 4.4)
  * Dimension by dimension: L = -(Fhat_{i+1/2,j} - Fhat_{i-1/2,j})/dx - (Ghat_{i,j+1/2} -
  * Ghat_{i,j-1/2})/dy (eq:2d), each a 1D WENO-ZN reconstruction of the Lax-Friedrichs split

@@ -45,6 +45,8 @@ SIGNATURES = [
     ("wzn_rhs_1d", _I32, [_PP, _P, _P, _I64, _D, _P, _P]),
     ("wzn_rk3_run_1d", _I32, [_PP, _P, _P, _I64, _D, _D, _I32, _P, _P, _P, _P, _P, _P]),
     ("wzn_rk3_step_1d", _I32, [_PP, _P, _P, _I64, _D, _D, _P, _P, _P, _P]),
+    ("wzn_rhs_1d_char", _I32, [_PP, _P, _P, _I64, _D, _P, _P, _P]),
+    ("wzn_rk3_run_1d_char", _I32, [_PP, _P, _P, _I64, _D, _D, _I32, _P, _P, _P, _P, _P, _P]),
     ("wzn_rhs_2d", _I32, [_PP, _P, _P, _I64, _I64, _D, _D, _P, _P]),
     ("wzn_rk3_run_2d", _I32, [_PP, _P, _P, _I64, _I64, _D, _D, _D, _I32, _P, _P, _P, _P]),
     ("wzn_rk3_step_2d", _I32, [_PP, _P, _P, _I64, _I64, _D, _D, _D, _P, _P, _P, _P]),

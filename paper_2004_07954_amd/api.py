@@ -139,6 +139,51 @@ def rk3_step_1d(u, dx, cfl=0.5, prm=None, dt=None, stage=None):
     return dt_o
 
 
+def rhs_1d_char(u, dx, prm=None, alpha3=None, out=None):
+    """L(u) for 1D Euler u[3, n] with the reconstruction in local characteristic fields.
+    alpha3: None (reduced from u, or prm.lf_alpha_x for all three if >= 0) or 3 frozen
+    per-field alphas."""
+    prm = prm or params()
+    _check_state(u, 3)
+    out = torch.empty_like(u) if out is None else out
+    _check_state(out, 3, "out")
+    al = _dev_f64(alpha3, 3, "alpha3", u.device)
+    check(lib().wzn_rhs_1d_char(C.byref(prm), _ptr(u), _ptr(out), u.shape[1], float(dx),
+                                _ptr(al), _ptr(workspace(u.device)), _stream()))
+    return out
+
+
+def rk3_run_1d_char(u, dx, nsteps, cfl=0.5, prm=None, dt=None, alpha=None, stage=None,
+                    record=False):
+    """Advance 1D Euler u[3, n] in place by nsteps TVD-RK3 steps of the characteristic scheme.
+
+    dt: None (CFL from U^n) or [nsteps]; alpha: None or [nsteps, 3, 3] frozen per-stage,
+    per-field alphas.  With record=True returns (dt[nsteps], alpha[nsteps, 3, 3])."""
+    prm = prm or params()
+    _check_state(u, 3)
+    n = u.shape[1]
+    if stage is None:
+        stage = torch.empty((2,) + tuple(u.shape), dtype=u.dtype, device=u.device)
+    if stage.numel() < 2 * u.numel() or not stage.is_contiguous() or stage.dtype != u.dtype:
+        raise ValueError("stage must be a contiguous fp64 tensor of 2 * u.numel() elements")
+    if dt is None:
+        dt_t = None
+    elif isinstance(dt, (int, float)):
+        dt_t = torch.full((nsteps,), float(dt), dtype=torch.float64, device=u.device)
+    else:
+        dt_t = _dev_f64(dt, nsteps, "dt", u.device)
+    al_t = _dev_f64(alpha, 9 * nsteps, "alpha", u.device)
+    dt_o = torch.empty(nsteps, dtype=torch.float64, device=u.device) if record else None
+    al_o = torch.empty(9 * nsteps, dtype=torch.float64, device=u.device) if record else None
+    check(lib().wzn_rk3_run_1d_char(C.byref(prm), _ptr(u), _ptr(stage), n, float(dx),
+                                    float(cfl), int(nsteps), _ptr(dt_t), _ptr(al_t),
+                                    _ptr(dt_o), _ptr(al_o), _ptr(workspace(u.device)),
+                                    _stream()))
+    if record:
+        return dt_o, al_o.view(nsteps, 3, 3)
+    return None
+
+
 def _check_state_2d(u, name="u"):
     if not isinstance(u, torch.Tensor) or not u.is_cuda:
         raise TypeError("%s must be a CUDA (HIP) tensor" % name)

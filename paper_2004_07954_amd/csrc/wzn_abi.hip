@@ -208,6 +208,36 @@ int32_t wzn_rk3_step_1d(const wzn_params* p, void* u, void* stage, int64_t n, do
   return wzn_rk3_run_1d(p, u, stage, n, dx, cfl, 1, dt_in, nullptr, dt_out, nullptr, ws, stream);
 }
 
+int32_t wzn_rhs_1d_char(const wzn_params* p, const void* u, void* dudt, int64_t n, double dx,
+                        const double* alpha3, void* ws, void* stream) {
+  g_err[0] = 0;
+  int st = check_1d(p, n, dx, ws);
+  if (st) return st;
+  if (p->system != WZN_EULER)
+    return set_error(WZN_ERR_ARG, "characteristic fields exist for the Euler system only");
+  if (!u || !dudt) return set_error(WZN_ERR_ARG, "u or dudt is NULL");
+  if (u == dudt) return set_error(WZN_ERR_ARG, "u and dudt must not alias");
+  Workspace w = make_workspace(ws);
+  return rhs_1d_char(p, (const double*)u, (double*)dudt, n, dx, alpha3, &w, (hipStream_t)stream);
+}
+
+int32_t wzn_rk3_run_1d_char(const wzn_params* p, void* u, void* stage, int64_t n, double dx,
+                            double cfl, int32_t nsteps, const double* dt_in,
+                            const double* alpha_in, double* dt_out, double* alpha_out, void* ws,
+                            void* stream) {
+  g_err[0] = 0;
+  int st = check_1d(p, n, dx, ws);
+  if (st) return st;
+  if (p->system != WZN_EULER)
+    return set_error(WZN_ERR_ARG, "characteristic fields exist for the Euler system only");
+  if (!u || !stage) return set_error(WZN_ERR_ARG, "u or stage is NULL");
+  if (nsteps < 0) return set_error(WZN_ERR_ARG, "nsteps < 0");
+  if (!dt_in && !(cfl > 0.0)) return set_error(WZN_ERR_ARG, "cfl must be positive");
+  Workspace w = make_workspace(ws);
+  return rk3_run_1d_char(p, (double*)u, (double*)stage, n, dx, cfl, nsteps, dt_in, alpha_in,
+                         dt_out, alpha_out, &w, (hipStream_t)stream);
+}
+
 int32_t wzn_rhs_2d(const wzn_params* p, const void* u, void* dudt, int64_t nx, int64_t ny,
                    double dx, double dy, void* ws, void* stream) {
   g_err[0] = 0;

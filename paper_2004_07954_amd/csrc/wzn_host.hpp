@@ -14,10 +14,11 @@ struct Workspace {
   unsigned long long* speed_y;  // [3] ring of max(|v|+c) slots (y direction)
   double* dt;                   // [1] dt of the current step
   unsigned long long* counter;  // [1] work-queue counter (batched launch)
+  unsigned long long* char_speed;  // [3][3] ring of per-field alpha triples (characteristic)
   unsigned long long* scratch;  // [WS_SCRATCH_WORDS] spare words
 };
 constexpr int WS_WORDS = 512;  // 4 KiB
-constexpr int WS_SCRATCH_WORDS = WS_WORDS - 16;
+constexpr int WS_SCRATCH_WORDS = WS_WORDS - 32;
 
 inline Workspace make_workspace(void* ws) {
   unsigned long long* w = (unsigned long long*)ws;
@@ -26,7 +27,8 @@ inline Workspace make_workspace(void* ws) {
   s.speed_y = w + 3;
   s.dt = (double*)(w + 6);
   s.counter = w + 7;
-  s.scratch = w + 16;
+  s.char_speed = w + 16;
+  s.scratch = w + 32;
   return s;
 }
 
@@ -61,6 +63,12 @@ int batched_rk3_run_1d(const wzn_params* p, double* u, double* stage, int64_t to
                        const int64_t* offsets, const double* dx, const int32_t* order,
                        int32_t batch, int32_t nsteps, double cfl, const wzn_batch_tuning* tn,
                        double* dt_out, Workspace* ws, hipStream_t s);
+
+int rhs_1d_char(const wzn_params* p, const double* u, double* dudt, int64_t n, double dx,
+                const double* alpha3, Workspace* ws, hipStream_t s);
+int rk3_run_1d_char(const wzn_params* p, double* u, double* stage, int64_t n, double dx,
+                    double cfl, int32_t nsteps, const double* dt_in, const double* alpha_in,
+                    double* dt_out, double* alpha_out, Workspace* ws, hipStream_t s);
 
 int rhs_1d_vjp(const wzn_params* p, const double* u, const double* mu, double* out, int64_t n,
                double dx, Workspace* ws, hipStream_t s);
