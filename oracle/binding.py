@@ -67,6 +67,10 @@ def lib():
                                          C.POINTER(OrcParams), d, p]
         L.orc_rhs_1d_char_f64.argtypes = [i32, i64, p, p, d, p, C.POINTER(OrcParams), d, p]
         L.orc_roe_eigen_f64.argtypes = [p, p, d, p, p]
+        L.orc_rhs_2d_sw_f64.argtypes = [i32, i32, i64, i64, p, p, d, d, C.POINTER(OrcParams), d]
+        L.orc_sw_split_f64.argtypes = [p, i32, d, p, p]
+        L.orc_rk3_run_2d_sw_f64.argtypes = [i32, i32, i64, i64, p, d, d, d, C.c_int32, p,
+                                            C.POINTER(OrcParams), d, p]
         L.orc_rk3_run_1d_char_f64.argtypes = [i32, i64, p, d, d, C.c_int32,
                                               C.POINTER(OrcParams), d, p, p]
         L.orc_num_threads.restype = C.c_int
@@ -199,6 +203,39 @@ def rk3_run_2d(u, dx, dy, nsteps, cfl=0.5, dt=None, bcx=BC_TRANSMISSIVE, bcy=BC_
     dt_out = np.zeros(nsteps)
     lib().orc_rk3_run_2d_f64(bcx, bcy, nx, ny, _ptr(u), dx, dy, cfl, nsteps, _ptr(dt),
                              C.byref(prm), gamma, _ptr(dt_out))
+    return u, dt_out
+
+
+def rhs_2d_sw(u, dx, dy, bcx=BC_TRANSMISSIVE, bcy=None, prm=None, gamma=GAMMA):
+    """2D Euler L(U) with the Steger-Warming splitting, [4, ny, nx]."""
+    prm = prm or params()
+    bcy = bcx if bcy is None else bcy
+    u = _f64(u)
+    ny, nx = u.shape[-2], u.shape[-1]
+    out = np.zeros_like(u)
+    lib().orc_rhs_2d_sw_f64(bcx, bcy, nx, ny, _ptr(u), _ptr(out), dx, dy, C.byref(prm), gamma)
+    return out
+
+
+def sw_split(U, direction, gamma=GAMMA):
+    """(F+, F-) of one 2D state along direction 0 (x) or 1 (y)."""
+    Fp, Fm = np.zeros(4), np.zeros(4)
+    lib().orc_sw_split_f64(_ptr(_f64(U)), int(direction), gamma, _ptr(Fp), _ptr(Fm))
+    return Fp, Fm
+
+
+def rk3_run_2d_sw(u, dx, dy, nsteps, cfl=0.5, bcx=BC_TRANSMISSIVE, bcy=None, dt=None,
+                  prm=None, gamma=GAMMA):
+    """nsteps TVD-RK3 steps with the Steger-Warming splitting; returns (u, dt[nsteps])."""
+    prm = prm or params()
+    bcy = bcx if bcy is None else bcy
+    u = _f64(u).copy()
+    ny, nx = u.shape[-2], u.shape[-1]
+    if dt is not None:
+        dt = _f64(np.broadcast_to(np.asarray(dt, dtype=np.float64), (nsteps,)))
+    dt_out = np.zeros(nsteps)
+    lib().orc_rk3_run_2d_sw_f64(bcx, bcy, nx, ny, _ptr(u), dx, dy, cfl, nsteps, _ptr(dt),
+                                C.byref(prm), gamma, _ptr(dt_out))
     return u, dt_out
 
 

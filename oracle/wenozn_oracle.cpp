@@ -55,6 +55,8 @@ static inline cplx absv(cplx z) {
   return cplx(0.0, 0.0);
 }
 
+static inline double sqrtv(double x) { return std::sqrt(x); }
+
 static inline double realv(double x) { return x; }
 static inline double realv(f128 x) { return (double)x; }
 static inline double realv(cplx z) { return z.real(); }
@@ -180,6 +182,38 @@ static void euler2_speeds(const double* U, const Phys& ph, double* sx, double* s
   *sy = std::fabs(v) + c;
 }
 
+// Steger-Warming flux-vector splitting of the 2D Euler flux along the unit direction
+// (nx, ny) = (1, 0) for F or (0, 1) for G (Sec. 4.4 cites it; the ideal-gas form).  With the
+// normal velocity un, the eigenvalues l = (un - c, un, un, un + c) and l^{+-} = (l +- |l|)/2,
+//   F^{+-} = rho/(2 gamma) * ( 2(gamma-1) l2 + l1 + l4,
+//                              2(gamma-1) l2 u + l1 (u - c nx) + l4 (u + c nx),
+//                              2(gamma-1) l2 v + l1 (v - c ny) + l4 (v + c ny),
+//                              (gamma-1) l2 (u^2 + v^2) + l1/2 ((u - c nx)^2 + (v - c ny)^2)
+//                                + l4/2 ((u + c nx)^2 + (v + c ny)^2)
+//                                + (3 - gamma)(l1 + l4) c^2 / (2 (gamma - 1)) ).
+// No entropy fix: |l| is used as it is.  F^+ + F^- = F (exactly, in exact arithmetic).
+template <class T>
+static void sw_split(const T* U, int dir, int sign, T* Fs, const Phys& ph) {
+  const T g = T(ph.gamma);
+  const T rho = U[0], u = U[1] / rho, v = U[2] / rho;
+  const T p = (g - T(1)) * (U[3] - rho / T(2) * (u * u + v * v));
+  const T c = sqrtv(g * p / rho);
+  const T nx = dir == 0 ? T(1) : T(0), ny = dir == 0 ? T(0) : T(1);
+  const T un = dir == 0 ? u : v;
+  const T s = sign > 0 ? T(1) : T(-1);
+  const T l1 = (un - c + s * absv(un - c)) / T(2);
+  const T l2 = (un + s * absv(un)) / T(2);
+  const T l4 = (un + c + s * absv(un + c)) / T(2);
+  const T k = rho / (T(2) * g);
+  const T um = u - c * nx, vm = v - c * ny, up = u + c * nx, vp = v + c * ny;
+  Fs[0] = k * (T(2) * (g - T(1)) * l2 + l1 + l4);
+  Fs[1] = k * (T(2) * (g - T(1)) * l2 * u + l1 * um + l4 * up);
+  Fs[2] = k * (T(2) * (g - T(1)) * l2 * v + l1 * vm + l4 * vp);
+  Fs[3] = k * ((g - T(1)) * l2 * (u * u + v * v) + l1 / T(2) * (um * um + vm * vm) +
+               l4 / T(2) * (up * up + vp * vp) +
+               (T(3) - g) * (l1 + l4) * c * c / (T(2) * (g - T(1))));
+}
+
 static int nvar_of(int sys) { return sys == SYS_ADV ? 1 : (sys == SYS_EULER1 ? 3 : 4); }
 
 // Ghost index map for three ghost cells per side (Sec. 4.2, eq:26 periodic; the
@@ -257,8 +291,6 @@ static void rhs_1d(int sys, int bc, int64_t n, const T* u, T* dudt, T dx, double
 //     cells, alpha_k = max over interior cells of |lambda_k(U_j)|, lambda = (u - c, u, u + c),
 //     recomputed per RHS evaluation;
 //   * ghat_k = WZN(g+_{i-2..i+2}) + WZN(g-_{i+3..i-1}) (mirrored), fhat = R ghat.
-static inline double sqrtv(double x) { return std::sqrt(x); }
-
 template <class T>
 static void roe_eigen(const T* UL, const T* UR, const Phys& ph, T R[3][3], T Lc[3][3]) {
   const T g = T(ph.gamma);
@@ -355,12 +387,14 @@ static void rhs_1d_char(int bc, int64_t n, const T* u, T* dudt, T dx, const doub
 
 // ---------------------------------------------------------------- 2D right-hand side
 // Dimension by dimension (Sec. 4.4, eq:2d): L = -(Fhat_{i+1/2,j} - Fhat_{i-1/2,j})/dx
-// - (Ghat_{i,j+1/2} - Ghat_{i,j-1/2})/dy, each a 1D WENO-ZN reconstruction of the
-// Lax-Friedrichs-split flux along its own direction with its own global alpha.
-// Layout [4][ny][nx], x fastest.
+// - (Ghat_{i,j+1/2} - Ghat_{i,j-1/2})/dy, each a 1D WENO-ZN reconstruction of the split
+// flux along its own direction: Lax-Friedrichs with its own global alpha (split = 0), or the
+// Steger-Warming splitting the paper uses for its 2D problems (split = 1; the alphas are not
+// used).  Layout [4][ny][nx], x fastest.
+enum { SPLIT_LF = 0, SPLIT_SW = 1 };
 template <class T>
 static void rhs_2d(int bcx, int bcy, int64_t nx, int64_t ny, const T* u, T* dudt, T dx, T dy,
-                   double ax, double ay, const OrcParams& P, const Phys& ph) {
+                   double ax, double ay, const OrcParams& P, const Phys& ph, int split = SPLIT_LF) {
   const int64_t N = nx * ny;
 #pragma omp parallel for
   for (int64_t j = 0; j < ny; ++j) {
@@ -369,12 +403,13 @@ static void rhs_2d(int bcx, int bcy, int64_t nx, int64_t ny, const T* u, T* dudt
     std::vector<T> fp(4 * np), fm(4 * np), fh(4 * (nx + 1));
     for (int64_t g = -3; g < nx + 3; ++g) {
       const int64_t gi = ghost_index(g, nx, bcx);
-      T U[4], F[4], G[4];
+      T U[4], F[4], G[4], Sp[4], Sm[4];
       for (int v = 0; v < 4; ++v) U[v] = u[v * N + j * nx + gi];
       euler2_flux(U, F, G, ph);
+      if (split == SPLIT_SW) { sw_split(U, 0, +1, Sp, ph); sw_split(U, 0, -1, Sm, ph); }
       for (int v = 0; v < 4; ++v) {
-        fp[v * np + g + 3] = T(1) / T(2) * (F[v] + T(ax) * U[v]);
-        fm[v * np + g + 3] = T(1) / T(2) * (F[v] - T(ax) * U[v]);
+        fp[v * np + g + 3] = split == SPLIT_SW ? Sp[v] : T(1) / T(2) * (F[v] + T(ax) * U[v]);
+        fm[v * np + g + 3] = split == SPLIT_SW ? Sm[v] : T(1) / T(2) * (F[v] - T(ax) * U[v]);
       }
     }
     for (int64_t k = 0; k <= nx; ++k) {
@@ -398,12 +433,13 @@ static void rhs_2d(int bcx, int bcy, int64_t nx, int64_t ny, const T* u, T* dudt
     std::vector<T> gp(4 * np), gm(4 * np), gh(4 * (ny + 1));
     for (int64_t g = -3; g < ny + 3; ++g) {
       const int64_t gj = ghost_index(g, ny, bcy);
-      T U[4], F[4], G[4];
+      T U[4], F[4], G[4], Sp[4], Sm[4];
       for (int v = 0; v < 4; ++v) U[v] = u[v * N + gj * nx + i];
       euler2_flux(U, F, G, ph);
+      if (split == SPLIT_SW) { sw_split(U, 1, +1, Sp, ph); sw_split(U, 1, -1, Sm, ph); }
       for (int v = 0; v < 4; ++v) {
-        gp[v * np + g + 3] = T(1) / T(2) * (G[v] + T(ay) * U[v]);
-        gm[v * np + g + 3] = T(1) / T(2) * (G[v] - T(ay) * U[v]);
+        gp[v * np + g + 3] = split == SPLIT_SW ? Sp[v] : T(1) / T(2) * (G[v] + T(ay) * U[v]);
+        gm[v * np + g + 3] = split == SPLIT_SW ? Sm[v] : T(1) / T(2) * (G[v] - T(ay) * U[v]);
       }
     }
     for (int64_t k = 0; k <= ny; ++k) {
@@ -617,6 +653,45 @@ void orc_rk3_run_2d_f64(int bcx, int bcy, int64_t nx, int64_t ny, double* u, dou
       double ax, ay;
       lf_alpha_2d(nx * ny, us.data(), ph, &ax, &ay);
       rhs_2d<double>(bcx, bcy, nx, ny, us.data(), L.data(), dx, dy, ax, ay, *P, ph);
+      for (int64_t k = 0; k < M; ++k)
+        us[k] = RK_A[s] * un[k] + RK_B[s] * (us[k] + dt * L[k]);
+    }
+    std::memcpy(u, us.data(), sizeof(double) * M);
+    if (dt_out) dt_out[st] = dt;
+  }
+}
+
+// ---- 2D RHS with the Steger-Warming splitting (fp64).
+void orc_rhs_2d_sw_f64(int bcx, int bcy, int64_t nx, int64_t ny, const double* u, double* dudt,
+                       double dx, double dy, const OrcParams* P, double gamma) {
+  Phys ph{0.0, gamma};
+  rhs_2d<double>(bcx, bcy, nx, ny, u, dudt, dx, dy, 0.0, 0.0, *P, ph, SPLIT_SW);
+}
+
+// ---- Steger-Warming split fluxes of one 2D state along dir (0: x, 1: y): Fp, Fm [4].
+void orc_sw_split_f64(const double* U, int dir, double gamma, double* Fp, double* Fm) {
+  Phys ph{0.0, gamma};
+  sw_split<double>(U, dir, +1, Fp, ph);
+  sw_split<double>(U, dir, -1, Fm, ph);
+}
+
+// ---- nsteps TVD-RK3 steps, 2D, Steger-Warming splitting, in place; dt as in
+// orc_rk3_run_2d_f64 (Sec. 4.4).
+void orc_rk3_run_2d_sw_f64(int bcx, int bcy, int64_t nx, int64_t ny, double* u, double dx,
+                           double dy, double cfl, int32_t nsteps, const double* dt_in,
+                           const OrcParams* P, double gamma, double* dt_out) {
+  Phys ph{0.0, gamma};
+  const int64_t M = 4 * nx * ny;
+  std::vector<double> un(M), us(M), L(M);
+  for (int32_t st = 0; st < nsteps; ++st) {
+    std::memcpy(un.data(), u, sizeof(double) * M);
+    std::memcpy(us.data(), u, sizeof(double) * M);
+    double sx, sy;
+    lf_alpha_2d(nx * ny, u, ph, &sx, &sy);
+    const double dtx = dx / sx, dty = dy / sy;
+    const double dt = dt_in ? dt_in[st] : cfl * dtx * dty / (dtx + dty);
+    for (int s = 0; s < 3; ++s) {
+      rhs_2d<double>(bcx, bcy, nx, ny, us.data(), L.data(), dx, dy, 0.0, 0.0, *P, ph, SPLIT_SW);
       for (int64_t k = 0; k < M; ++k)
         us[k] = RK_A[s] * un[k] + RK_B[s] * (us[k] + dt * L[k]);
     }

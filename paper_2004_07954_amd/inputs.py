@@ -166,6 +166,37 @@ def four_quadrant_random(nx, ny, seed=3, gamma=GAMMA):
     return prim_to_cons_2d(prim[0], prim[1], prim[2], prim[3], gamma), dx, dy
 
 
+# The two 2D Riemann problems of Sec. 4.4 on [0, 1]^2 (eq:RM1, split at (0.8, 0.8), run to
+# t = 0.8 on 400^2; eq:RM2, split at (0.5, 0.5), run to t = 0.25 on 1200^2 and 2400^2), as
+# (rho, u, v, p) per quadrant.  Cells on a split line belong to the quadrant the equation's
+# inequalities give them.
+def riemann_2d(case, nx, ny=None, gamma=GAMMA):
+    """Initial data of the 2D Riemann case 1 or 2; returns (U[4, ny, nx], dx, dy)."""
+    ny = nx if ny is None else ny
+    x, dx = cell_centres(0.0, 1.0, nx)
+    y, dy = cell_centres(0.0, 1.0, ny)
+    X, Y = np.meshgrid(x, y)
+    prim = np.zeros((4, ny, nx))
+    if case == 1:
+        east, north = X >= 0.8, Y >= 0.8
+        quads = [(east & north, (1.5, 0.0, 0.0, 1.5)),
+                 (~east & north, (0.5323, 1.206, 0.0, 0.3)),
+                 (~east & ~north, (0.138, 1.206, 1.206, 0.029)),
+                 (east & ~north, (0.5323, 0.0, 1.206, 0.3))]
+    elif case == 2:
+        east, north = X > 0.5, Y > 0.5
+        quads = [(~east & ~north, (0.8, 0.0, 0.0, 1.0)),
+                 (~east & north, (1.0, 0.7276, 0.0, 1.0)),
+                 (east & ~north, (1.0, 0.0, 0.7276, 1.0)),
+                 (east & north, (0.5313, 0.0, 0.0, 0.4))]
+    else:
+        raise ValueError("case must be 1 or 2")
+    for mask, st in quads:
+        for c in range(4):
+            prim[c][mask] = st[c]
+    return prim_to_cons_2d(prim[0], prim[1], prim[2], prim[3], gamma), dx, dy
+
+
 def density_wave_2d(nx, ny, amp=0.2, u0=1.0, v0=0.5, p0=1.0, t=0.0, gamma=GAMMA):
     """rho = 1 + amp sin(pi (x + y - (u0 + v0) t)) on the periodic [-1, 1]^2."""
     x, dx = cell_centres(-1.0, 1.0, nx)
