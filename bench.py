@@ -90,19 +90,27 @@ def cpu_baseline(n, budget_s=12.0):
                       "%.1f s" % (steps, 3 * steps, n, el)}
 
 
-def bench_2d(steps, dtype_name, warmup=3):
-    """Secondary figure: 2D Euler dimension-by-dimension WENO-ZN, 4096^2 four-quadrant data,
-    transmissive, CFL 0.5 (one step = row kernel + column kernel per stage)."""
+def bench_2d(steps, dtype_name, warmup=3, split="lf"):
+    """Secondary figure: 2D Euler dimension-by-dimension WENO-ZN, transmissive, CFL 0.5 (one
+    step = row kernel + column kernel per stage): the global Lax-Friedrichs split on 4096^2
+    four-quadrant data, or the paper's own setup, the Steger-Warming split on its second
+    Riemann case at its finest grid, 2400^2 (Sec. 4.4)."""
     import torch
     from paper_2004_07954_amd import api, inputs as I
-    nx = ny = 4096
     tdt = torch.float64 if dtype_name == "f64" else torch.float32
-    u0, dx, dy = I.four_quadrant_random(nx, ny, seed=3)
+    if split == "sw":
+        nx = ny = 2400
+        u0, dx, dy = I.riemann_2d(2, nx)
+        wl = "euler2d_riemann_case2_steger_warming_%dx%d" % (nx, ny)
+    else:
+        nx = ny = 4096
+        u0, dx, dy = I.four_quadrant_random(nx, ny, seed=3)
+        wl = "euler2d_four_quadrant_%dx%d" % (nx, ny)
     u0t = torch.tensor(u0, dtype=tdt, device="cuda")
     u = u0t.clone()
     stage = torch.empty((2, 4, ny, nx), dtype=tdt, device="cuda")
     prm = api.params("euler", dtype="fp64" if dtype_name == "f64" else "fp32",
-                     eps=1e-40 if dtype_name == "f64" else 1e-30)
+                     eps=1e-40 if dtype_name == "f64" else 1e-30, split=split)
     api.rk3_run_2d(u, dx, dy, warmup, prm=prm, stage=stage)
     u.copy_(u0t)
     torch.cuda.synchronize()
@@ -118,7 +126,7 @@ def bench_2d(steps, dtype_name, warmup=3):
     bytes_stage = nx * ny * 4 * esz * (2 + 3 + 3) / 3.0
     stage_ms = ms / (3 * steps)
     gbs = bytes_stage / (stage_ms * 1e-3) / 1e9
-    return {"workload": "euler2d_four_quadrant_%dx%d" % (nx, ny), "dtype": dtype_name,
+    return {"workload": wl, "dtype": dtype_name,
             "steps": steps, "ms_per_step": ms / steps,
             "value": nx * ny * 3 * steps / (ms * 1e-3), "unit": "cell-RHS/s",
             "stage_ms": stage_ms, "hbm_gbs_algorithmic": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}
@@ -405,7 +413,9 @@ def main():
     if not args.no_2d:
         log("2D fp64 and fp32, 4096^2")
         rec["secondary"] = {"euler2d_f64": bench_2d(args.steps_2d, "f64"),
-                            "euler2d_f32": bench_2d(args.steps_2d, "f32")}
+                            "euler2d_f32": bench_2d(args.steps_2d, "f32"),
+                            "euler2d_sw_f64": bench_2d(args.steps_2d, "f64", split="sw"),
+                            "euler2d_sw_f32": bench_2d(args.steps_2d, "f32", split="sw")}
     if not args.no_batched:
         log("batched: 4096 shock tubes")
         rec.setdefault("secondary", {})["batched"] = bench_batched(args.steps_batched)

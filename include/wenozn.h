@@ -54,6 +54,7 @@ enum {
 enum { WZN_ADVECTION = 0, WZN_EULER = 1 };          /* system */
 enum { WZN_FP64 = 0, WZN_FP32 = 1 };               /* dtype */
 enum { WZN_PERIODIC = 0, WZN_TRANSMISSIVE = 1 };   /* boundary condition per direction */
+enum { WZN_SPLIT_LF = 0, WZN_SPLIT_SW = 1 };        /* flux splitting */
 
 typedef struct {
   uint32_t abi_version; /* must equal WZN_ABI_VERSION */
@@ -63,7 +64,8 @@ typedef struct {
                            cell into the three ghost cells */
   int32_t p_C;          /* exponent of the ratio inside C (eq:function): must be 2 */
   int32_t q;            /* exponent on tau8/(IS_k+eps) (eq:new): must be 1 */
-  int32_t reserved;
+  int32_t flux_split;   /* WZN_SPLIT_LF (global Lax-Friedrichs, every entry point) or
+                           WZN_SPLIT_SW (Steger-Warming, Sec. 4.4: 2D entry points only) */
   double adv_speed;     /* a of u_t + a u_x = 0 (advection only) */
   double gamma;         /* ratio of specific heats, Sec. 4.3: 1.4 */
   double A;             /* constant of eq:function: 10 */
@@ -158,8 +160,14 @@ int32_t wzn_rk3_run_1d_char(const wzn_params* p, void* u, void* stage, int64_t n
 
 /* ---------------------------------------------------------------- 2D (Euler, Sec. 4.4)
  * Dimension by dimension: L = -(Fhat_{i+1/2,j} - Fhat_{i-1/2,j})/dx - (Ghat_{i,j+1/2} -
- * Ghat_{i,j-1/2})/dy (eq:2d), each a 1D WENO-ZN reconstruction of the Lax-Friedrichs split
- * flux with its own global alpha (alpha_x = max(|u| + c), alpha_y = max(|v| + c)).
+ * Ghat_{i,j-1/2})/dy (eq:2d), each a 1D WENO-ZN reconstruction, component by component, of
+ * the split flux along its direction:
+ *   p->flux_split == WZN_SPLIT_LF: Lax-Friedrichs with its own global alpha
+ *     (alpha_x = max(|u| + c), alpha_y = max(|v| + c));
+ *   p->flux_split == WZN_SPLIT_SW: Steger-Warming flux-vector splitting, the paper's 2D
+ *     setup: F^{+-} = R diag((lambda +- |lambda|)/2) R^{-1} U per cell with the eigenvalues
+ *     (u_n - c, u_n, u_n, u_n + c) of the flux Jacobian along the direction (no alphas; the
+ *     lf_alpha fields are ignored).
  * p->dtype selects fp64 (arrays of double) or fp32 (arrays of float; the weights use a
  * scale-safe normalisation and eps must be >= 1e-36, e.g. 1e-30).
  * u, dudt: [4][ny][nx], x fastest; bc_x / bc_y select the boundary in each direction.

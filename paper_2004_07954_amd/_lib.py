@@ -15,12 +15,13 @@ WZN_ERR_UNSUPPORTED = 6
 WZN_ADVECTION, WZN_EULER = 0, 1
 WZN_FP64, WZN_FP32 = 0, 1
 WZN_PERIODIC, WZN_TRANSMISSIVE = 0, 1
+WZN_SPLIT_LF, WZN_SPLIT_SW = 0, 1
 
 
 class WznParams(C.Structure):
     _fields_ = [("abi_version", C.c_uint32), ("system", C.c_int32), ("dtype", C.c_int32),
                 ("bc_x", C.c_int32), ("bc_y", C.c_int32), ("p_C", C.c_int32), ("q", C.c_int32),
-                ("reserved", C.c_int32), ("adv_speed", C.c_double), ("gamma", C.c_double),
+                ("flux_split", C.c_int32), ("adv_speed", C.c_double), ("gamma", C.c_double),
                 ("A", C.c_double), ("eps", C.c_double), ("lf_alpha_x", C.c_double),
                 ("lf_alpha_y", C.c_double)]
 

@@ -13,11 +13,13 @@ from ._lib import WznParams, check, lib
 
 SYSTEMS = {"advection": _lib.WZN_ADVECTION, "euler": _lib.WZN_EULER}
 BCS = {"periodic": _lib.WZN_PERIODIC, "transmissive": _lib.WZN_TRANSMISSIVE}
+SPLITS = {"lf": _lib.WZN_SPLIT_LF, "sw": _lib.WZN_SPLIT_SW}
 
 
 def params(system="euler", bc="transmissive", bc_y=None, adv_speed=1.0, gamma=1.4, A=10.0,
-           eps=1e-40, lf_alpha=None, lf_alpha_y=None, dtype="fp64"):
-    """WENO-ZN parameters; defaults are the paper's (A = 10, eps = 1e-40, gamma = 1.4)."""
+           eps=1e-40, lf_alpha=None, lf_alpha_y=None, dtype="fp64", split="lf"):
+    """WENO-ZN parameters; defaults are the paper's (A = 10, eps = 1e-40, gamma = 1.4).
+    split: "lf" (global Lax-Friedrichs) or "sw" (Steger-Warming, 2D only)."""
     p = WznParams()
     lib().wzn_default_params(C.byref(p), SYSTEMS[system])
     p.bc_x = BCS[bc]
@@ -29,6 +31,7 @@ def params(system="euler", bc="transmissive", bc_y=None, adv_speed=1.0, gamma=1.
     p.lf_alpha_x = -1.0 if lf_alpha is None else float(lf_alpha)
     p.lf_alpha_y = -1.0 if lf_alpha_y is None else float(lf_alpha_y)
     p.dtype = {"fp64": _lib.WZN_FP64, "fp32": _lib.WZN_FP32}[dtype]
+    p.flux_split = SPLITS[split]
     return p
 
 

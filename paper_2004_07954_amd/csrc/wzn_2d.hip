@@ -34,9 +34,11 @@ struct ColArgs {
   double dx, dy;
   int bc;
   int mode;
+  int split;      // SPLIT_LF, or SPLIT_SW (alpha is then unused)
   int seg;        // rows per segment (a multiple of the tile height)
   double rk_a, rk_b;
   double gamma, eps_s, A;
+  double inv_gamma, inv_gm1;  // 1 / gamma, 1 / (gamma - 1) (Steger-Warming split)
   const unsigned long long* alpha_slot;  // alpha_y
   const double* alpha_arr;
   double alpha_const;
@@ -83,7 +85,7 @@ __device__ __forceinline__ void flux_y(const T (&U)[4], T (&G)[4], T gm1) {
 // LDS), or at the segment's first row the boundary interface, reconstructed once per segment.
 // Four waves per SIMD (128 VGPRs; the fp64 variant with the wave-speed epilogue spills a few
 // bytes, which costs far less than dropping to three waves).
-template <int NG, int K, typename T, bool SPEED>
+template <int NG, int K, typename T, bool SPEED, bool SW>
 __global__ __launch_bounds__(64 * NG) __attribute__((amdgpu_waves_per_eu(4)))
 void col_kernel(ColArgs<T> a) {
   static_assert(NG >= 4, "the segment's boundary interface uses one group per component");
@@ -127,6 +129,7 @@ void col_kernel(ColArgs<T> a) {
   }
 
   const T gm1 = T(a.gamma) - T(1);
+  const T gam = T(a.gamma), inv_gam = T(a.inv_gamma), inv_gm1 = T(a.inv_gm1);
   const T eps_s = T(a.eps_s), A = window_const<T>(a.A);
   const T coef = T(-0.5 / a.dy);
   const T cdt = a.mode == MODE_STAGE ? T(a.rk_b * dt) : T(1);
@@ -153,10 +156,16 @@ void col_kernel(ColArgs<T> a) {
 #pragma unroll
         for (int j = 0; j < K; ++j) {
           T G[4];
-          flux_y<T>(Ureg[j], G, gm1);
           const int p = 3 + g * K + j;
+          if constexpr (SW) {
+            sw_flux2<1, false, T>(Ureg[j], G, gm1, gam, inv_gam, inv_gm1);
 #pragma unroll
-          for (int c = 0; c < 4; ++c) W[(c * NPOS + p) * 64 + col] = fma_t(alpha, Ureg[j][c], G[c]);
+            for (int c = 0; c < 4; ++c) W[(c * NPOS + p) * 64 + col] = G[c];
+          } else {
+            flux_y<T>(Ureg[j], G, gm1);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) W[(c * NPOS + p) * 64 + col] = fma_t(alpha, Ureg[j][c], G[c]);
+          }
         }
         if (g < 3) {
 #pragma unroll
@@ -167,33 +176,62 @@ void col_kernel(ColArgs<T> a) {
 #pragma unroll
             for (int c = 0; c < 4; ++c) HU[hh][c] = a.uin[c * a.plane + gi];
             T G[4];
-            flux_y<T>(HU[hh], G, gm1);
+            if constexpr (SW) {
+              // (the second phase re-reads the halo state rather than holding it)
+              sw_flux2<1, false, T>(HU[hh], G, gm1, gam, inv_gam, inv_gm1);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) W[(c * NPOS + p) * 64 + col] = fma_t(alpha, HU[hh][c], G[c]);
+              for (int c = 0; c < 4; ++c) W[(c * NPOS + p) * 64 + col] = G[c];
+            } else {
+              flux_y<T>(HU[hh], G, gm1);
+#pragma unroll
+              for (int c = 0; c < 4; ++c) W[(c * NPOS + p) * 64 + col] = fma_t(alpha, HU[hh][c], G[c]);
+            }
           }
         }
       } else {
-        // w^- from the staged w^+ of the same slot
+        // w^- from the staged w^+ of the same slot (Lax-Friedrichs) or from the state
+        // (Steger-Warming)
 #pragma unroll
         for (int j = 0; j < K; ++j) {
           const int p = 3 + g * K + j;
+          if constexpr (SW) {
+            T G[4];
+            sw_flux2<1, true, T>(Ureg[j], G, gm1, gam, inv_gam, inv_gm1);
 #pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            T& w = W[(c * NPOS + p) * 64 + col];
-            w = fma_t(m2a, Ureg[j][c], w);
+            for (int c = 0; c < 4; ++c) W[(c * NPOS + p) * 64 + col] = G[c];
+          } else {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+              T& w = W[(c * NPOS + p) * 64 + col];
+              w = fma_t(m2a, Ureg[j][c], w);
+            }
           }
         }
         if (g < 3) {
 #pragma unroll
           for (int hh = 0; hh < 2; ++hh) {
             const int p = hh == 0 ? g : TY + 3 + g;
+            if constexpr (SW) {
+              T Uh[4], G[4];
+              const int yy = bc_cell(y0 + p - 3, ny, a.bc);
+              const int64_t gi = (int64_t)yy * nx + xc;
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-              T& w = W[(c * NPOS + p) * 64 + col];
-              w = fma_t(m2a, HU[hh][c], w);
+              for (int c = 0; c < 4; ++c) Uh[c] = a.uin[c * a.plane + gi];
+              sw_flux2<1, true, T>(Uh, G, gm1, gam, inv_gam, inv_gm1);
+#pragma unroll
+              for (int c = 0; c < 4; ++c) W[(c * NPOS + p) * 64 + col] = G[c];
+            } else {
+#pragma unroll
+              for (int c = 0; c < 4; ++c) {
+                T& w = W[(c * NPOS + p) * 64 + col];
+                w = fma_t(m2a, HU[hh][c], w);
+              }
             }
           }
         }
+        // (Steger-Warming: keep the loads below from being hoisted into the split arithmetic
+        // above, where their registers would be live at the same time)
+        if constexpr (SW) asm volatile("" ::: "memory");
         // the state is not needed past this point: replace it by the base of the output,
         // Lx (RHS) or fma(b_s dt, Lx, fma(a_s, U^n, b_s U)) (stage), so that the output is
         // fma(cdt, Ly, base) with cdt = 1 or b_s dt
@@ -324,12 +362,14 @@ static int launch_col_t(ColArgs<T> a, hipStream_t s) {
   nseg = (a.ny + seg - 1) / seg;
   a.seg = (int)seg;
   if (bx > 0x7fffffff || nseg > 65535) return set_error(WZN_ERR_SIZE, "grid too large (columns)");
-  if (a.speed_next_x)
-    hipLaunchKernelGGL((col_kernel<NG, K, T, true>), dim3((unsigned)bx, (unsigned)nseg),
-                       dim3(64 * NG), 0, s, a);
-  else
-    hipLaunchKernelGGL((col_kernel<NG, K, T, false>), dim3((unsigned)bx, (unsigned)nseg),
-                       dim3(64 * NG), 0, s, a);
+  const dim3 grid((unsigned)bx, (unsigned)nseg), block(64 * NG);
+  if (a.split == SPLIT_SW) {
+    if (a.speed_next_x) hipLaunchKernelGGL((col_kernel<NG, K, T, true, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((col_kernel<NG, K, T, false, true>), grid, block, 0, s, a);
+  } else {
+    if (a.speed_next_x) hipLaunchKernelGGL((col_kernel<NG, K, T, true, false>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((col_kernel<NG, K, T, false, false>), grid, block, 0, s, a);
+  }
   return check_launch("col_kernel");
 }
 
@@ -349,7 +389,10 @@ static RowArgs<T> row_args(const wzn_params* p, int64_t nx, int64_t ny, double d
   a.dx = dx;
   a.bc = p->bc_x;
   a.mode = MODE_RHS;
+  a.split = p->flux_split;
   a.gamma = p->gamma;
+  a.inv_gamma = 1.0 / p->gamma;
+  a.inv_gm1 = 1.0 / (p->gamma - 1.0);
   a.eps_s = 16.0 * p->eps;
   a.A = p->A;
   return a;
@@ -364,7 +407,10 @@ static ColArgs<T> col_args(const wzn_params* p, int64_t nx, int64_t ny, double d
   a.dx = dx;
   a.dy = dy;
   a.bc = p->bc_y;
+  a.split = p->flux_split;
   a.gamma = p->gamma;
+  a.inv_gamma = 1.0 / p->gamma;
+  a.inv_gm1 = 1.0 / (p->gamma - 1.0);
   a.eps_s = 16.0 * p->eps;
   a.A = p->A;
   return a;
@@ -386,16 +432,18 @@ int rhs_2d_t(const wzn_params* p, const T* u, T* dudt, int64_t nx, int64_t ny, d
              double dy, Workspace* ws, hipStream_t s) {
   RowArgs<T> ra = row_args<T>(p, nx, ny, dx);
   ColArgs<T> ca = col_args<T>(p, nx, ny, dx, dy);
-  const bool reduce = p->lf_alpha_x < 0.0 || p->lf_alpha_y < 0.0;
+  // the Steger-Warming split has no alpha
+  const bool sw = p->flux_split == SPLIT_SW;
+  const bool reduce = !sw && (p->lf_alpha_x < 0.0 || p->lf_alpha_y < 0.0);
   if (reduce) {
     int st = launch_zero_words(ws->speed, 6, s);
     if (st) return st;
     st = launch_speed_max<T>(u, nx * ny, 4, p->gamma, &ws->speed[0], &ws->speed_y[0], s);
     if (st) return st;
   }
-  if (p->lf_alpha_x >= 0.0) ra.alpha_const = p->lf_alpha_x;
+  if (p->lf_alpha_x >= 0.0 || sw) ra.alpha_const = p->lf_alpha_x;
   else ra.alpha_slot = &ws->speed[0];
-  if (p->lf_alpha_y >= 0.0) ca.alpha_const = p->lf_alpha_y;
+  if (p->lf_alpha_y >= 0.0 || sw) ca.alpha_const = p->lf_alpha_y;
   else ca.alpha_slot = &ws->speed_y[0];
   ra.uin = u;
   ra.out = dudt;
@@ -422,7 +470,9 @@ int rk3_run_2d_t(const wzn_params* p, T* u, T* stage, int64_t nx, int64_t ny, do
   const int64_t M = 4 * nx * ny;
   T* U1 = stage;
   T* U2 = stage + M;
-  const bool reduce_x = p->lf_alpha_x < 0.0, reduce_y = p->lf_alpha_y < 0.0;
+  // the Steger-Warming split has no alpha: the speed slots then serve the CFL dt only
+  const bool sw = p->flux_split == SPLIT_SW;
+  const bool reduce_x = !sw && p->lf_alpha_x < 0.0, reduce_y = !sw && p->lf_alpha_y < 0.0;
   const bool need_speed = reduce_x || reduce_y || dt_in == nullptr;
   unsigned long long* rx = ws->speed;
   unsigned long long* ry = ws->speed_y;

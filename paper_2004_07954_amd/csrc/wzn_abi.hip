@@ -63,6 +63,8 @@ static int check_params(const wzn_params* p, bool allow_fp32) {
     return set_error(WZN_ERR_ARG, "unknown bc_y %d", p->bc_y);
   if (p->p_C != 2 || p->q != 1)
     return set_error(WZN_ERR_UNSUPPORTED, "only p_C = 2, q = 1 (the paper's weights) run here");
+  if (p->flux_split != WZN_SPLIT_LF && p->flux_split != WZN_SPLIT_SW)
+    return set_error(WZN_ERR_ARG, "unknown flux_split %d", p->flux_split);
   if (!(p->eps > 0.0) || !(p->A > 0.0))
     return set_error(WZN_ERR_ARG, "eps and A must be positive");
   if (p->system == WZN_EULER && !(p->gamma > 1.0))
@@ -75,6 +77,8 @@ static int check_params(const wzn_params* p, bool allow_fp32) {
 static int check_1d(const wzn_params* p, int64_t n, double dx, void* ws) {
   int st = check_params(p, false);
   if (st) return st;
+  if (p->flux_split != WZN_SPLIT_LF)
+    return set_error(WZN_ERR_UNSUPPORTED, "the 1D entry points use the Lax-Friedrichs split");
   if (n < 6) return set_error(WZN_ERR_SIZE, "n = %lld < 6", (long long)n);
   if (n > (int64_t)1 << 30)
     return set_error(WZN_ERR_SIZE, "n = %lld > 2^30 cells per row", (long long)n);

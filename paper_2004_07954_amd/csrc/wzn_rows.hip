@@ -14,7 +14,7 @@ namespace wzn {
 
 // SPEED (a.speed_next set) is a template parameter rather than a branch: one kernel holding
 // both inlined tile variants is register-allocated for their union.
-template <int NT, int K, int SYS, typename T, bool SPLIT, bool SPEED>
+template <int NT, int K, int SYS, typename T, bool SPLIT, bool SPEED, bool SW>
 __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T* W = reinterpret_cast<T*>(lds_raw);
@@ -42,7 +42,7 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
   const int64_t g0 = (int64_t)blockIdx.x * (NT * K);
   const int64_t rowoff = (int64_t)blockIdx.y * a.row_stride;
   double smax = 0.0;
-  row_tile<NT, K, SYS, T, SPEED, SPLIT>(a, g0, rowoff, T(alpha_d), dt, W, EX, smax);
+  row_tile<NT, K, SYS, T, SPEED, SPLIT, SW>(a, g0, rowoff, T(alpha_d), dt, W, EX, smax);
   if constexpr (SPEED) {
     const double m = block_max<NT>(smax, red);
     if (tid == 0) atomic_max_pos(a.speed_next, m);
@@ -52,30 +52,34 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
 }
 
 // ------------------------------------------------------------------ host side
-template <int NT, int K, int SYS, typename T, bool SPLIT, bool SPEED>
+template <int NT, int K, int SYS, typename T, bool SPLIT, bool SPEED, bool SW = false>
 static int launch_row_ts(const RowArgs<T>& a, int64_t rows, hipStream_t s) {
   constexpr int TT = NT * K;
   const int64_t blocks = (a.n + TT - 1) / TT;
   const size_t lds = tile_lds_bytes<NT, K, SYS, T, SPLIT>();
   static bool attr_set = false;
   if (!attr_set) {
-    if (hipFuncSetAttribute((const void*)row_kernel<NT, K, SYS, T, SPLIT, SPEED>,
+    if (hipFuncSetAttribute((const void*)row_kernel<NT, K, SYS, T, SPLIT, SPEED, SW>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
       return set_error(WZN_ERR_HIP, "hipFuncSetAttribute(row_kernel) failed");
     attr_set = true;
   }
   if (blocks > 0x7fffffff || rows > 65535)
     return set_error(WZN_ERR_SIZE, "grid too large for the row kernel");
-  hipLaunchKernelGGL((row_kernel<NT, K, SYS, T, SPLIT, SPEED>),
+  hipLaunchKernelGGL((row_kernel<NT, K, SYS, T, SPLIT, SPEED, SW>),
                      dim3((unsigned)blocks, (unsigned)rows), dim3(NT), lds, s, a);
   return check_launch("row_kernel");
 }
 
 template <int NT, int K, int SYS, typename T, bool SPLIT = false>
 static int launch_row_t(const RowArgs<T>& a, int64_t rows, hipStream_t s) {
-  // the wave-speed epilogue exists for the 1D Euler system only
+  // the wave-speed epilogue exists for the 1D Euler system only, the Steger-Warming split for
+  // the 2D x sweep only
   if constexpr (SYS == SYS_EULER1) {
     if (a.speed_next) return launch_row_ts<NT, K, SYS, T, SPLIT, true>(a, rows, s);
+  }
+  if constexpr (SYS == SYS_EULER2X) {
+    if (a.split == SPLIT_SW) return launch_row_ts<NT, K, SYS, T, SPLIT, false, true>(a, rows, s);
   }
   return launch_row_ts<NT, K, SYS, T, SPLIT, false>(a, rows, s);
 }

@@ -9,6 +9,7 @@ namespace wzn {
 
 enum { SYS_ADV = 0, SYS_EULER1 = 1, SYS_EULER2X = 2 };
 enum { MODE_RHS = 0, MODE_STAGE = 1 };
+enum { SPLIT_LF = 0, SPLIT_SW = 1 };  // flux splitting (the values of wzn_params.flux_split)
 
 template <typename T>
 struct RowArgs {
@@ -21,8 +22,10 @@ struct RowArgs {
   double dx;
   int bc;
   int mode;
+  int split;           // SPLIT_LF, or SPLIT_SW (2D x sweep only; alpha is then unused)
   double rk_a, rk_b;
   double adv, gamma, eps_s, A;
+  double inv_gamma, inv_gm1;  // 1 / gamma, 1 / (gamma - 1) (Steger-Warming split)
   // LF alpha of this RHS evaluation: slot (reduced) / array (frozen) / constant
   const unsigned long long* alpha_slot;
   const double* alpha_arr;

@@ -72,6 +72,38 @@ __device__ __forceinline__ void row_flux(const T* U, T* F, T adv, T gm1) {
   }
 }
 
+// Twice the Steger-Warming split flux, w = 2 F^{+-} (Sec. 4.4 cites the splitting), of a 2D
+// Euler state along x (DIR = 0: normal velocity u, tangential v) or y (DIR = 1), for the sign
+// NEG = false (+) or true (-).  With the eigenvalues (un - c, un, un + c) split as
+// l^{+-} = max(l, 0) / min(l, 0) (the same bits as (l +- |l|) / 2), S = l1 + l4, Dl = l4 - l1,
+// s0 = 2 (gamma - 1) l2 + S and k = rho / gamma, the ideal-gas form
+//   w = k (s0, un s0 + c Dl [normal], ut s0 [tangential], q2 s0 / 2 + c (S c / (gamma - 1) + un Dl))
+// (q2 = u^2 + v^2) is the textbook F^{+-} = rho/(2 gamma) (...) with the energy terms collected.
+template <int DIR, bool NEG, typename T>
+__device__ __forceinline__ void sw_flux2(const T* U, T (&w)[4], T gm1, T gam, T inv_gamma,
+                                         T inv_gm1) {
+#pragma clang fp contract(off)
+  const T rho = U[0];
+  const T r = rcp_nr(rho);
+  const T u = U[1] * r, v = U[2] * r;
+  const T p = gm1 * fma_t(-(T(0.5) * U[2]), v, fma_t(-(T(0.5) * U[1]), u, U[3]));
+  const T c = sqrt_gs((gam * p) * r);
+  const T un = DIR == 0 ? u : v, ut = DIR == 0 ? v : u;
+  const T l1 = NEG ? fmin(un - c, T(0)) : fmax(un - c, T(0));
+  const T l2 = NEG ? fmin(un, T(0)) : fmax(un, T(0));
+  const T l4 = NEG ? fmin(un + c, T(0)) : fmax(un + c, T(0));
+  const T S = l1 + l4, Dl = l4 - l1;
+  const T s0 = fma_t(T(2) * gm1, l2, S);
+  const T k = rho * inv_gamma;
+  const T q2 = fma_t(u, u, v * v);
+  w[0] = k * s0;
+  const T wn = k * fma_t(un, s0, c * Dl);
+  const T wt = k * (ut * s0);
+  w[1] = DIR == 0 ? wn : wt;
+  w[2] = DIR == 0 ? wt : wn;
+  w[3] = k * fma_t(T(0.5) * q2, s0, c * fma_t(S * c, inv_gm1, un * Dl));
+}
+
 // Largest wave speed |u| + c of a 1D state, c = sqrt(gamma p / rho), in a fixed operation
 // order so that every kernel that needs it (reductions, stage epilogues, the batched launch)
 // gets the same bits.
@@ -202,9 +234,10 @@ constexpr int tile_ex_elems() { return (8 + NT / 64) * SysInfo<SYS>::NV; }
 // interface of the previous lane (cross-lane permute), of the previous wave (LDS) or, for the
 // tile's first cell, the boundary interface.  W: dynamic LDS of tile_lds_bytes(); EX: LDS of
 // tile_ex_elems() elements.  All threads of the workgroup must call it (it contains barriers).
-template <int NT, int K, int SYS, typename T, bool SPEED, bool SPLIT = false>
+template <int NT, int K, int SYS, typename T, bool SPEED, bool SPLIT = false, bool SW = false>
 __device__ __forceinline__ void row_tile(const RowArgs<T>& a, int64_t g0l, int64_t rowoff,
                                          T alpha, double dt, T* W, T* EX, double& smax) {
+  static_assert(!SW || SYS == SYS_EULER2X, "the Steger-Warming split is for the 2D x sweep");
   using TL = Tile<NT, K>;
   constexpr int TT = TL::T;
   constexpr int NV = SysInfo<SYS>::NV;
@@ -217,6 +250,7 @@ __device__ __forceinline__ void row_tile(const RowArgs<T>& a, int64_t g0l, int64
   const T adv = T(a.adv);
   const T eps_s = T(a.eps_s), A = window_const<T>(a.A);
   const T m2a = -T(2) * alpha;
+  const T gam = T(a.gamma), inv_gam = T(a.inv_gamma), inv_gm1 = T(a.inv_gm1);
   const int c0 = g0 + tid * K;          // first own cell
   const bool full = g0 + TT <= n;       // every own cell is a row cell (uniform)
   T* HU = EX + 2 * NV;                  // [6][NV] halo cells' U
@@ -245,14 +279,25 @@ __device__ __forceinline__ void row_tile(const RowArgs<T>& a, int64_t g0l, int64
       }
 #pragma unroll
       for (int j = 0; j < K; ++j) {
-        T F[NV];
-        row_flux<SYS, T>(Ureg[j], F, adv, gm1);
         const int q = tpos<NT, K>(3 + tid * K + j);
+        if constexpr (SW) {
+          T wp[NV], wm[NV];
+          sw_flux2<0, false, T>(Ureg[j], wp, gm1, gam, inv_gam, inv_gm1);
+          if (!SPLIT) sw_flux2<0, true, T>(Ureg[j], wm, gm1, gam, inv_gam, inv_gm1);
 #pragma unroll
-        for (int c = 0; c < NV; ++c) {
-          const T wp = fma_t(alpha, Ureg[j][c], F[c]);
-          W[(NS * c) * TL::SZ + q] = wp;
-          if (!SPLIT) W[(NS * c + 1) * TL::SZ + q] = fma_t(m2a, Ureg[j][c], wp);
+          for (int c = 0; c < NV; ++c) {
+            W[(NS * c) * TL::SZ + q] = wp[c];
+            if (!SPLIT) W[(NS * c + 1) * TL::SZ + q] = wm[c];
+          }
+        } else {
+          T F[NV];
+          row_flux<SYS, T>(Ureg[j], F, adv, gm1);
+#pragma unroll
+          for (int c = 0; c < NV; ++c) {
+            const T wp = fma_t(alpha, Ureg[j][c], F[c]);
+            W[(NS * c) * TL::SZ + q] = wp;
+            if (!SPLIT) W[(NS * c + 1) * TL::SZ + q] = fma_t(m2a, Ureg[j][c], wp);
+          }
         }
       }
       // ---- halo cells -3, -2, -1, T, T+1, T+2 on threads 0..5
@@ -262,28 +307,57 @@ __device__ __forceinline__ void row_tile(const RowArgs<T>& a, int64_t g0l, int64
         T U[NV], F[NV];
 #pragma unroll
         for (int c = 0; c < NV; ++c) U[c] = a.uin[c * a.plane + rowoff + cell];
-        row_flux<SYS, T>(U, F, adv, gm1);
         const int q = tpos<NT, K>(p);
+        if constexpr (SW) {
+          T wp[NV], wm[NV];
+          sw_flux2<0, false, T>(U, wp, gm1, gam, inv_gam, inv_gm1);
+          if (!SPLIT) sw_flux2<0, true, T>(U, wm, gm1, gam, inv_gam, inv_gm1);
 #pragma unroll
-        for (int c = 0; c < NV; ++c) {
-          const T wp = fma_t(alpha, U[c], F[c]);
-          W[(NS * c) * TL::SZ + q] = wp;
-          if (!SPLIT) W[(NS * c + 1) * TL::SZ + q] = fma_t(m2a, U[c], wp);
-          else HU[tid * NV + c] = U[c];
+          for (int c = 0; c < NV; ++c) {
+            W[(NS * c) * TL::SZ + q] = wp[c];
+            if (!SPLIT) W[(NS * c + 1) * TL::SZ + q] = wm[c];
+            else HU[tid * NV + c] = U[c];
+          }
+        } else {
+          row_flux<SYS, T>(U, F, adv, gm1);
+#pragma unroll
+          for (int c = 0; c < NV; ++c) {
+            const T wp = fma_t(alpha, U[c], F[c]);
+            W[(NS * c) * TL::SZ + q] = wp;
+            if (!SPLIT) W[(NS * c + 1) * TL::SZ + q] = fma_t(m2a, U[c], wp);
+            else HU[tid * NV + c] = U[c];
+          }
         }
       }
     } else {
       // ---- second phase of the split layout: w^- from the staged w^+ of the same slot
+      //      (Lax-Friedrichs) or from the state (Steger-Warming)
 #pragma unroll
       for (int j = 0; j < K; ++j) {
         const int q = tpos<NT, K>(3 + tid * K + j);
+        if constexpr (SW) {
+          T wm[NV];
+          sw_flux2<0, true, T>(Ureg[j], wm, gm1, gam, inv_gam, inv_gm1);
 #pragma unroll
-        for (int c = 0; c < NV; ++c) W[c * TL::SZ + q] = fma_t(m2a, Ureg[j][c], W[c * TL::SZ + q]);
+          for (int c = 0; c < NV; ++c) W[c * TL::SZ + q] = wm[c];
+        } else {
+#pragma unroll
+          for (int c = 0; c < NV; ++c)
+            W[c * TL::SZ + q] = fma_t(m2a, Ureg[j][c], W[c * TL::SZ + q]);
+        }
       }
       if (tid < 6) {
         const int q = tpos<NT, K>(tid < 3 ? tid : TT + tid);
+        if constexpr (SW) {
+          T wm[NV];
+          sw_flux2<0, true, T>(HU + tid * NV, wm, gm1, gam, inv_gam, inv_gm1);
 #pragma unroll
-        for (int c = 0; c < NV; ++c) W[c * TL::SZ + q] = fma_t(m2a, HU[tid * NV + c], W[c * TL::SZ + q]);
+          for (int c = 0; c < NV; ++c) W[c * TL::SZ + q] = wm[c];
+        } else {
+#pragma unroll
+          for (int c = 0; c < NV; ++c)
+            W[c * TL::SZ + q] = fma_t(m2a, HU[tid * NV + c], W[c * TL::SZ + q]);
+        }
       }
       if (a.mode == MODE_STAGE) {
         // U is not needed past this point: replace it by the stage base a_s U^n + b_s U (the
