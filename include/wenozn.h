@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define WZN_ABI_VERSION 1
+#define WZN_ABI_VERSION 2
 
 enum {
   WZN_OK = 0,
@@ -55,6 +55,7 @@ enum { WZN_ADVECTION = 0, WZN_EULER = 1 };          /* system */
 enum { WZN_FP64 = 0, WZN_FP32 = 1 };               /* dtype */
 enum { WZN_PERIODIC = 0, WZN_TRANSMISSIVE = 1 };   /* boundary condition per direction */
 enum { WZN_SPLIT_LF = 0, WZN_SPLIT_SW = 1 };        /* flux splitting */
+enum { WZN_WEIGHTS_ZN = 0, WZN_WEIGHTS_Z = 1 };    /* nonlinear weights */
 
 typedef struct {
   uint32_t abi_version; /* must equal WZN_ABI_VERSION */
@@ -73,10 +74,17 @@ typedef struct {
   double lf_alpha_x;    /* < 0: alpha_x = max(|u| + c) of each RHS input (Euler) or |a|
                            (advection); >= 0: this frozen value */
   double lf_alpha_y;    /* same for the y direction (2D) */
+  int32_t weights;      /* WZN_WEIGHTS_ZN: the paper's weights (eq:new), every entry point;
+                           WZN_WEIGHTS_Z: the WENO-Z weights with q = 1 that the paper compares
+                           against (Sec. 2.2, eq:15), alpha_k = c_k (1 + tau5/(IS_k + eps)):
+                           wzn_rhs_1d, wzn_rk3_run_1d, wzn_rk3_step_1d and wzn_reconstruct
+                           only (others return WZN_ERR_UNSUPPORTED) */
+  int32_t pad;          /* unused */
 } wzn_params;
 
 /* Fill *p with the paper's values for `system`: A = 10, eps = 1e-40, p_C = 2, q = 1,
- * gamma = 1.4, a = 1, fp64, transmissive (Euler) or periodic (advection), alphas reduced. */
+ * gamma = 1.4, a = 1, fp64, transmissive (Euler) or periodic (advection), alphas reduced,
+ * Lax-Friedrichs split, WENO-ZN weights. */
 void wzn_default_params(wzn_params* p, int32_t system);
 
 int32_t wzn_abi_version(void);
@@ -104,6 +112,17 @@ int32_t wzn_get_row_tuning(int32_t nvar, int64_t n, int32_t* nt, int32_t* k, int
 /* Bytes of device workspace `ws` needed by any entry point for grids up to nx * ny cells
  * (ny = 1 in 1D).  Currently a small constant. */
 size_t wzn_workspace_bytes(const wzn_params* p, int64_t nx, int64_t ny);
+
+/* ---------------------------------------------------------------- reconstruction
+ * wzn_reconstruct: fhat[i] = the fifth-order WENO value at x_{i+1/2} (Sec. 2.1, eq:3 with the
+ * candidates of eq:4 and the normalised weights of eq:5) from the five point values
+ * f[0 * m + i] .. f[4 * m + i] = f_{i-2} .. f_{i+2}, for 0 <= i < m; the weights are
+ * p->weights (WENO-ZN: eq:isjiang, eq:tau, eq:tau8, eq:function, eq:new with p->A, p->eps;
+ * or WENO-Z), fp64.  f [5][m] and fhat [m] are device arrays (structure of arrays); the
+ * value from the other side of an interface is the same call with the stencil mirrored.
+ * m <= 2^34; m = 0 enqueues nothing. */
+int32_t wzn_reconstruct(const wzn_params* p, const double* f, double* fhat, int64_t m,
+                        void* stream);
 
 /* ---------------------------------------------------------------- 1D
  * wzn_rhs_1d: dudt = L(u) (eq:2) for one state u[nvar][n].  u and dudt must not alias.

@@ -9,13 +9,14 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libwenozn.so")
 
-WZN_ABI_VERSION = 1
+WZN_ABI_VERSION = 2
 WZN_OK, WZN_ERR_ARG, WZN_ERR_SIZE, WZN_ERR_DTYPE, WZN_ERR_HIP = 0, 1, 2, 3, 4
 WZN_ERR_UNSUPPORTED = 6
 WZN_ADVECTION, WZN_EULER = 0, 1
 WZN_FP64, WZN_FP32 = 0, 1
 WZN_PERIODIC, WZN_TRANSMISSIVE = 0, 1
 WZN_SPLIT_LF, WZN_SPLIT_SW = 0, 1
+WZN_WEIGHTS_ZN, WZN_WEIGHTS_Z = 0, 1
 
 
 class WznParams(C.Structure):
@@ -23,7 +24,7 @@ class WznParams(C.Structure):
                 ("bc_x", C.c_int32), ("bc_y", C.c_int32), ("p_C", C.c_int32), ("q", C.c_int32),
                 ("flux_split", C.c_int32), ("adv_speed", C.c_double), ("gamma", C.c_double),
                 ("A", C.c_double), ("eps", C.c_double), ("lf_alpha_x", C.c_double),
-                ("lf_alpha_y", C.c_double)]
+                ("lf_alpha_y", C.c_double), ("weights", C.c_int32), ("pad", C.c_int32)]
 
 
 class WznBatchTuning(C.Structure):
@@ -43,6 +44,7 @@ SIGNATURES = [
     ("wzn_get_row_tuning", _I32, [_I32, _I64, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                   C.POINTER(C.c_int32)]),
     ("wzn_workspace_bytes", _SZ, [_PP, _I64, _I64]),
+    ("wzn_reconstruct", _I32, [_PP, _P, _P, _I64, _P]),
     ("wzn_rhs_1d", _I32, [_PP, _P, _P, _I64, _D, _P, _P]),
     ("wzn_rk3_run_1d", _I32, [_PP, _P, _P, _I64, _D, _D, _I32, _P, _P, _P, _P, _P, _P]),
     ("wzn_rk3_step_1d", _I32, [_PP, _P, _P, _I64, _D, _D, _P, _P, _P, _P]),

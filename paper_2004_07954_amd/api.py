@@ -14,12 +14,14 @@ from ._lib import WznParams, check, lib
 SYSTEMS = {"advection": _lib.WZN_ADVECTION, "euler": _lib.WZN_EULER}
 BCS = {"periodic": _lib.WZN_PERIODIC, "transmissive": _lib.WZN_TRANSMISSIVE}
 SPLITS = {"lf": _lib.WZN_SPLIT_LF, "sw": _lib.WZN_SPLIT_SW}
+WEIGHTS = {"zn": _lib.WZN_WEIGHTS_ZN, "z": _lib.WZN_WEIGHTS_Z}
 
 
 def params(system="euler", bc="transmissive", bc_y=None, adv_speed=1.0, gamma=1.4, A=10.0,
-           eps=1e-40, lf_alpha=None, lf_alpha_y=None, dtype="fp64", split="lf"):
+           eps=1e-40, lf_alpha=None, lf_alpha_y=None, dtype="fp64", split="lf", weights="zn"):
     """WENO-ZN parameters; defaults are the paper's (A = 10, eps = 1e-40, gamma = 1.4).
-    split: "lf" (global Lax-Friedrichs) or "sw" (Steger-Warming, 2D only)."""
+    split: "lf" (global Lax-Friedrichs) or "sw" (Steger-Warming, 2D only); weights: "zn"
+    (the paper's) or "z" (WENO-Z, q = 1, the comparison scheme; 1D and reconstruct only)."""
     p = WznParams()
     lib().wzn_default_params(C.byref(p), SYSTEMS[system])
     p.bc_x = BCS[bc]
@@ -32,6 +34,7 @@ def params(system="euler", bc="transmissive", bc_y=None, adv_speed=1.0, gamma=1.
     p.lf_alpha_y = -1.0 if lf_alpha_y is None else float(lf_alpha_y)
     p.dtype = {"fp64": _lib.WZN_FP64, "fp32": _lib.WZN_FP32}[dtype]
     p.flux_split = SPLITS[split]
+    p.weights = WEIGHTS[weights]
     return p
 
 
@@ -84,6 +87,21 @@ def _dev_f64(x, n, name, device):
     if x.numel() != n:
         raise ValueError("%s must have %d entries" % (name, n))
     return x
+
+
+def reconstruct(f5, prm=None, out=None):
+    """fhat[m] from the point values f5[5, m] = (f_{i-2}, ..., f_{i+2}) of m stencils."""
+    prm = prm or params()
+    if not isinstance(f5, torch.Tensor) or not f5.is_cuda or f5.dtype != torch.float64:
+        raise TypeError("f5 must be a float64 CUDA (HIP) tensor")
+    if f5.dim() != 2 or f5.shape[0] != 5 or not f5.is_contiguous():
+        raise ValueError("f5 must be a contiguous [5, m] tensor")
+    m = f5.shape[1]
+    out = torch.empty(m, dtype=torch.float64, device=f5.device) if out is None else out
+    if out.numel() != m or out.dtype != torch.float64 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float64 tensor of m elements")
+    check(lib().wzn_reconstruct(C.byref(prm), _ptr(f5), _ptr(out), m, _stream()))
+    return out
 
 
 def rhs_1d(u, dx, prm=None, out=None):

@@ -89,6 +89,7 @@ static RowArgs<double> base_args(const wzn_params* p, int64_t n, double dx) {
   a.gamma = p->gamma;
   a.eps_s = 16.0 * p->eps;
   a.A = p->A;
+  a.weights = p->weights;
   return a;
 }
 
@@ -113,6 +114,34 @@ int rhs_1d(const wzn_params* p, const double* u, double* dudt, int64_t n, double
     a.alpha_slot = ws->speed;
   }
   return launch_rows(a, sys_of(p), 1, tuning_1d(nv, n), s);
+}
+
+// One reconstruction per thread from five point values (structure of arrays [5][m]).  The
+// window carries its indicators scaled by 4, so eps enters as 4 eps (see wzn_device.hpp).
+template <int WT>
+__global__ __launch_bounds__(256) void reconstruct_kernel(const double* __restrict__ f,
+                                                          double* __restrict__ fhat, int64_t m,
+                                                          double eps_s, double Aq) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < m;
+       i += (int64_t)gridDim.x * 256) {
+    double v[5], h[1];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) v[j] = f[j * m + i];
+    wzn_window<1, WT>(v, h, eps_s, Aq);
+    fhat[i] = h[0];
+  }
+}
+
+int reconstruct(const wzn_params* p, const double* f, double* fhat, int64_t m, hipStream_t s) {
+  int64_t blocks = (m + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (p->weights == WZN_WEIGHTS_Z)
+    hipLaunchKernelGGL((reconstruct_kernel<WEIGHTS_Z>), dim3((unsigned)blocks), dim3(256), 0, s,
+                       f, fhat, m, 4.0 * p->eps, 0.25 * p->A);
+  else
+    hipLaunchKernelGGL((reconstruct_kernel<WEIGHTS_ZN>), dim3((unsigned)blocks), dim3(256), 0, s,
+                       f, fhat, m, 4.0 * p->eps, 0.25 * p->A);
+  return check_launch("reconstruct_kernel");
 }
 
 static const double RK_A[3] = {0.0, 3.0 / 4.0, 1.0 / 3.0};

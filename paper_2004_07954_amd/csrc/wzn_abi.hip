@@ -49,7 +49,7 @@ Tuning1D tuning_1d(int nv, int64_t n) {
   return Tuning1D{256, 1, ROW_LDS_TILE};
 }
 
-static int check_params(const wzn_params* p, bool allow_fp32) {
+static int check_params(const wzn_params* p, bool allow_fp32, bool allow_z = false) {
   if (!p) return set_error(WZN_ERR_ARG, "params is NULL");
   if (p->abi_version != WZN_ABI_VERSION)
     return set_error(WZN_ERR_ARG, "abi_version %u != %d", p->abi_version, WZN_ABI_VERSION);
@@ -65,6 +65,11 @@ static int check_params(const wzn_params* p, bool allow_fp32) {
     return set_error(WZN_ERR_UNSUPPORTED, "only p_C = 2, q = 1 (the paper's weights) run here");
   if (p->flux_split != WZN_SPLIT_LF && p->flux_split != WZN_SPLIT_SW)
     return set_error(WZN_ERR_ARG, "unknown flux_split %d", p->flux_split);
+  if (p->weights != WZN_WEIGHTS_ZN && p->weights != WZN_WEIGHTS_Z)
+    return set_error(WZN_ERR_ARG, "unknown weights %d", p->weights);
+  if (p->weights == WZN_WEIGHTS_Z && !allow_z)
+    return set_error(WZN_ERR_UNSUPPORTED,
+                     "the WENO-Z weights run in wzn_rhs_1d, wzn_rk3_run_1d and wzn_reconstruct");
   if (!(p->eps > 0.0) || !(p->A > 0.0))
     return set_error(WZN_ERR_ARG, "eps and A must be positive");
   if (p->system == WZN_EULER && !(p->gamma > 1.0))
@@ -74,8 +79,8 @@ static int check_params(const wzn_params* p, bool allow_fp32) {
   return WZN_OK;
 }
 
-static int check_1d(const wzn_params* p, int64_t n, double dx, void* ws) {
-  int st = check_params(p, false);
+static int check_1d(const wzn_params* p, int64_t n, double dx, void* ws, bool allow_z = false) {
+  int st = check_params(p, false, allow_z);
   if (st) return st;
   if (p->flux_split != WZN_SPLIT_LF)
     return set_error(WZN_ERR_UNSUPPORTED, "the 1D entry points use the Lax-Friedrichs split");
@@ -181,10 +186,21 @@ size_t wzn_workspace_bytes(const wzn_params* p, int64_t nx, int64_t ny) {
   return sizeof(unsigned long long) * WS_WORDS;
 }
 
+int32_t wzn_reconstruct(const wzn_params* p, const double* f, double* fhat, int64_t m,
+                        void* stream) {
+  g_err[0] = 0;
+  int st = check_params(p, false, true);
+  if (st) return st;
+  if (m < 0 || m > ((int64_t)1 << 34)) return set_error(WZN_ERR_SIZE, "m out of range");
+  if (m == 0) return WZN_OK;  // (empty arrays may be NULL)
+  if (!f || !fhat) return set_error(WZN_ERR_ARG, "f or fhat is NULL");
+  return reconstruct(p, f, fhat, m, (hipStream_t)stream);
+}
+
 int32_t wzn_rhs_1d(const wzn_params* p, const void* u, void* dudt, int64_t n, double dx,
                    void* ws, void* stream) {
   g_err[0] = 0;
-  int st = check_1d(p, n, dx, ws);
+  int st = check_1d(p, n, dx, ws, true);
   if (st) return st;
   if (!u || !dudt) return set_error(WZN_ERR_ARG, "u or dudt is NULL");
   if (u == dudt) return set_error(WZN_ERR_ARG, "u and dudt must not alias");
@@ -196,7 +212,7 @@ int32_t wzn_rk3_run_1d(const wzn_params* p, void* u, void* stage, int64_t n, dou
                        double cfl, int32_t nsteps, const double* dt_in, const double* alpha_in,
                        double* dt_out, double* alpha_out, void* ws, void* stream) {
   g_err[0] = 0;
-  int st = check_1d(p, n, dx, ws);
+  int st = check_1d(p, n, dx, ws, true);
   if (st) return st;
   if (!u || !stage) return set_error(WZN_ERR_ARG, "u or stage is NULL");
   if (nsteps < 0) return set_error(WZN_ERR_ARG, "nsteps < 0");

@@ -102,7 +102,13 @@ template <> __device__ __forceinline__ float window_const<float>(double A) { ret
 // is one fma); per interface: tau5 = |s0 - s2|, num = (s0 + s2 - tau5) - eps (= IS0 + IS2 - tau5
 // + eps up to rounding, and only num^2 enters C), b = e_m - e_{m+1}, q1 = v_{m+2} + g_{m+2}/2
 // - D_{m+1}/6, q0 - q1 = e_m/3, q2 - q1 = e_{m+1}/6.
-template <int K>
+// WT selects the nonlinear weights: WEIGHTS_ZN, the paper's (Sec. 3, eq:new), or WEIGHTS_Z,
+// the WENO-Z weights with q = 1 the paper compares against (Sec. 2.2, eq:15),
+// alpha_k = c_k (1 + tau5/(IS_k + eps)).  In the product form above the latter is
+// B_k = prod_{j != k} s_j (s_k + tau5) (Aq unused), the same normalisation.
+enum { WEIGHTS_ZN = 0, WEIGHTS_Z = 1 };
+
+template <int K, int WT = WEIGHTS_ZN>
 __device__ __forceinline__ void wzn_window(const double* v, double* fh, double eps_s,
                                            double Aq) {
   constexpr int NG = K + 3;
@@ -132,17 +138,24 @@ __device__ __forceinline__ void wzn_window(const double* v, double* fh, double e
 
     const double d = s0 - s2;
     const double t5 = __builtin_fabs(d);
-    const double num = ((s0 + s2) - t5) - eps_s;
-    const double den = t5 + eps_s;
-    // tau8 (in the units of the scaled indicators) = (2 b)^2, b = D_m - 2 D_{m+1} + D_{m+2};
-    // H = tau8 den^2 / 4, G = A num^2 / 4
-    const double b = e[m] - e[m + 1];
-    const double bd = b * den;
-    const double H = bd * bd;
-    const double G = (Aq * num) * num;
-    const double t0 = __builtin_fma(G, s0, H);
-    const double t1 = __builtin_fma(G, s1, H);
-    const double t2 = __builtin_fma(G, s2, H);
+    double t0, t1, t2;
+    if constexpr (WT == WEIGHTS_Z) {
+      t0 = s0 + t5;
+      t1 = s1 + t5;
+      t2 = s2 + t5;
+    } else {
+      const double num = ((s0 + s2) - t5) - eps_s;
+      const double den = t5 + eps_s;
+      // tau8 (in the units of the scaled indicators) = (2 b)^2, b = D_m - 2 D_{m+1} + D_{m+2};
+      // H = tau8 den^2 / 4, G = A num^2 / 4
+      const double b = e[m] - e[m + 1];
+      const double bd = b * den;
+      const double H = bd * bd;
+      const double G = (Aq * num) * num;
+      t0 = __builtin_fma(G, s0, H);
+      t1 = __builtin_fma(G, s1, H);
+      t2 = __builtin_fma(G, s2, H);
+    }
     const double B0 = (s1 * s2) * t0;
     const double B1 = (s0 * s2) * t1;
     const double B2 = (s0 * s1) * t2;
@@ -167,8 +180,9 @@ __device__ __forceinline__ float fast_div(float num, float den) {
   return num * __builtin_amdgcn_rcpf(den);
 }
 
-template <int K>
+template <int K, int WT = WEIGHTS_ZN>
 __device__ __forceinline__ void wzn_window(const float* v, float* fh, float eps_s, float A) {
+  static_assert(WT == WEIGHTS_ZN, "fp32 runs the paper's weights only");
   constexpr int NG = K + 3;
   constexpr int ND = K + 2;
   float g[NG];

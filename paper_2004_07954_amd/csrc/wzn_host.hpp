@@ -82,6 +82,7 @@ int rk3_adjoint_1d(const wzn_params* p, const double* ckpts, int32_t nsteps, int
 
 int rhs_1d(const wzn_params* p, const double* u, double* dudt, int64_t n, double dx,
            Workspace* ws, hipStream_t s);
+int reconstruct(const wzn_params* p, const double* f, double* fhat, int64_t m, hipStream_t s);
 int rk3_run_1d(const wzn_params* p, double* u, double* stage, int64_t n, double dx, double cfl,
                int32_t nsteps, const double* dt_in, const double* alpha_in, double* dt_out,
                double* alpha_out, Workspace* ws, hipStream_t s);

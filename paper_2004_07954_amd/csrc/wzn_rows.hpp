@@ -23,6 +23,7 @@ struct RowArgs {
   int bc;
   int mode;
   int split;           // SPLIT_LF, or SPLIT_SW (2D x sweep only; alpha is then unused)
+  int weights;         // WEIGHTS_ZN, or WEIGHTS_Z (1D fp64 only)
   double rk_a, rk_b;
   double adv, gamma, eps_s, A;
   double inv_gamma, inv_gm1;  // 1 / gamma, 1 / (gamma - 1) (Steger-Warming split)

@@ -234,7 +234,8 @@ constexpr int tile_ex_elems() { return (8 + NT / 64) * SysInfo<SYS>::NV; }
 // interface of the previous lane (cross-lane permute), of the previous wave (LDS) or, for the
 // tile's first cell, the boundary interface.  W: dynamic LDS of tile_lds_bytes(); EX: LDS of
 // tile_ex_elems() elements.  All threads of the workgroup must call it (it contains barriers).
-template <int NT, int K, int SYS, typename T, bool SPEED, bool SPLIT = false, bool SW = false>
+template <int NT, int K, int SYS, typename T, bool SPEED, bool SPLIT = false, bool SW = false,
+          int WT = WEIGHTS_ZN>
 __device__ __forceinline__ void row_tile(const RowArgs<T>& a, int64_t g0l, int64_t rowoff,
                                          T alpha, double dt, T* W, T* EX, double& smax) {
   static_assert(!SW || SYS == SYS_EULER2X, "the Steger-Warming split is for the 2D x sweep");
@@ -396,7 +397,7 @@ __device__ __forceinline__ void row_tile(const RowArgs<T>& a, int64_t g0l, int64
         const int p = sg == 0 ? i : 5 - i;  // w^+ at cells -3..1; w^- mirrored, cells 2..-2
         v[i] = W[(NS * c + (SPLIT ? 0 : sg)) * TL::SZ + tpos<NT, K>(p)];
       }
-      wzn_window<1>(v, h, eps_s, A);
+      wzn_window<1, WT>(v, h, eps_s, A);
       EX[2 * c + sg] = h[0];
     }
 
@@ -409,7 +410,7 @@ __device__ __forceinline__ void row_tile(const RowArgs<T>& a, int64_t g0l, int64
 #pragma unroll
         for (int i = 0; i < K + 4; ++i)
           v[i] = W[(NS * c) * TL::SZ + ((1 + i) % K) * TL::LD + tid + (1 + i) / K];
-        wzn_window<K>(v, h, eps_s, A);
+        wzn_window<K, WT>(v, h, eps_s, A);
 #pragma unroll
         for (int m = 0; m < K; ++m) {
           fh[c][m] = h[m];
@@ -425,7 +426,7 @@ __device__ __forceinline__ void row_tile(const RowArgs<T>& a, int64_t g0l, int64
           const int pp = K + 5 - i;
           v[i] = W[(NS * c + NS - 1) * TL::SZ + (pp % K) * TL::LD + tid + pp / K];
         }
-        wzn_window<K>(v, h, eps_s, A);
+        wzn_window<K, WT>(v, h, eps_s, A);
 #pragma unroll
         for (int m = 0; m < K; ++m) {
           fh[c][m] += h[K - 1 - m];

@@ -1,0 +1,170 @@
+"""The WENO-Z comparison weights (Sec. 2.2, eq:15, q = 1) and the reconstruction entry point
+on the GPU: the paper's critical-point table reproduced by the GPU kernels (both its
+WENO-Z and its WENO-ZN column, the rows above fp64 resolution), parity of the WENO-Z right-
+hand side and runs against the oracle, and wzn_reconstruct against the oracle's
+reconstruction."""
+import mpmath as mp
+import numpy as np
+import pytest
+
+from conftest import read_golden
+from paper_2004_07954_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+RHS_TOL, RUN_TOL = 1e-12, 1e-10
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2004_07954_amd import api
+    return api
+
+
+def note(*args):
+    print("[gpu-case]", *args, flush=True)
+
+
+def normwise(gpu, ref):
+    gpu, ref = np.asarray(gpu), np.asarray(ref)
+    out = []
+    for c in range(ref.shape[0]):
+        scale = np.abs(ref[c]).max()
+        out.append(np.abs(gpu[c] - ref[c]).max() / (scale if scale > 0 else 1.0))
+    return max(out)
+
+
+def to_dev(x):
+    import torch
+    return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+# ---------------------------------------------------------------- Sec. 4.1, critical-point table
+@pytest.mark.parametrize("column,weights", [(4, "zn"), (2, "z")])
+def test_table3_on_gpu(api, column, weights):
+    """(fhat_{j+1/2} - fhat_{j-1/2})/dx at x_j = 0 for f = x^k e^x on 7 points (positive flux
+    only: advection with a = alpha = 1), through wzn_rhs_1d, against the printed errors.
+    Rows enter when their printed error is at least 2e5 times the fp64 resolution of the
+    difference quotient, 2.2e-16 max|f| / dx, so that the 5e-6 relative bound is met by any
+    correct fp64 evaluation order."""
+    prm = api.params("advection", bc="transmissive", lf_alpha=1.0, weights=weights)
+    used = 0
+    for row in read_golden("table3_critical_point.txt"):
+        k, m, printed = int(row[0]), int(row[1]), float(row[column])
+        dx = 0.025 / 2**m
+        xs = [mp.mpf(i) * mp.mpf("0.025") / 2**m for i in range(-3, 4)]
+        f = np.array([[float(x**k * mp.e**x) for x in xs]])
+        res = 2.2e-16 * np.abs(f).max() / dx
+        if printed < 2e5 * res:
+            continue
+        note("table3", weights, k, m)
+        L = api.rhs_1d(to_dev(f), dx, prm).cpu().numpy()
+        err = abs(-L[0, 3] - (1.0 if k == 1 else 0.0))
+        assert abs(err / printed - 1.0) < 5e-6, (k, m, err, printed)
+        used += 1
+    assert used >= 10
+
+
+# ---------------------------------------------------------------- WENO-Z RHS and runs
+@pytest.mark.parametrize("n", [6, 255, 1024, 4099])
+@pytest.mark.parametrize("bc", ["transmissive", "periodic"])
+def test_weno_z_rhs_euler(api, orc, n, bc):
+    note("rhs_1d weno-z euler", n, bc)
+    u = I.random_smooth_1d(n, seed=500 + n)
+    g = api.rhs_1d(to_dev(u), 1.0 / n, api.params("euler", bc=bc, weights="z")).cpu().numpy()
+    r, _ = orc.rhs_1d(u, 1.0 / n, bc=orc.BC_TRANSMISSIVE if bc == "transmissive" else orc.BC_PERIODIC,
+                      prm=orc.params(scheme=orc.ORC_Z, q=1))
+    assert normwise(g, r) <= RHS_TOL, normwise(g, r)
+
+
+def test_weno_z_rhs_shock_and_advection(api, orc):
+    note("rhs_1d weno-z shock / advection")
+    u, dx = I.shu_osher_like(4099)
+    g = api.rhs_1d(to_dev(u), dx, api.params("euler", weights="z")).cpu().numpy()
+    r, _ = orc.rhs_1d(u, dx, prm=orc.params(scheme=orc.ORC_Z, q=1))
+    assert normwise(g, r) <= RHS_TOL
+    a0, dx = I.advection_smooth(1000)
+    g = api.rhs_1d(to_dev(a0), dx, api.params("advection", bc="periodic", weights="z")).cpu().numpy()
+    r, _ = orc.rhs_1d(a0, dx, sys=orc.SYS_ADV, bc=orc.BC_PERIODIC,
+                      prm=orc.params(scheme=orc.ORC_Z, q=1))
+    assert normwise(g, r) <= RHS_TOL
+
+
+def test_weno_z_runs(api, orc):
+    """Smooth advection (200 steps) and the shock data (10 steps), with the dt history."""
+    note("rk3_run_1d weno-z")
+    a0, dx = I.advection_smooth(400)
+    ug = to_dev(a0)
+    api.rk3_run_1d(ug, dx, 200, cfl=0.5, prm=api.params("advection", bc="periodic", weights="z"))
+    r, _, _ = orc.rk3_run_1d(a0, dx, 200, cfl=0.5, sys=orc.SYS_ADV, bc=orc.BC_PERIODIC,
+                             prm=orc.params(scheme=orc.ORC_Z, q=1))
+    assert normwise(ug.cpu().numpy(), r) <= RUN_TOL
+    u0, dx = I.shu_osher_like(2048)
+    ug = to_dev(u0)
+    dtg, _ = api.rk3_run_1d(ug, dx, 10, cfl=0.5, prm=api.params("euler", weights="z"),
+                            record=True)
+    r, dtr, _ = orc.rk3_run_1d(u0, dx, 10, cfl=0.5, prm=orc.params(scheme=orc.ORC_Z, q=1))
+    assert np.allclose(dtg.cpu().numpy(), dtr, rtol=1e-13, atol=0)
+    assert normwise(ug.cpu().numpy(), r) <= RUN_TOL
+
+
+def test_weno_z_differs_from_zn(api):
+    """Control: the two weight families give different right-hand sides on shock data."""
+    u, dx = I.shu_osher_like(1000)
+    ud = to_dev(u)
+    a = api.rhs_1d(ud, dx, api.params("euler")).cpu().numpy()
+    b = api.rhs_1d(ud, dx, api.params("euler", weights="z")).cpu().numpy()
+    assert np.abs(a - b).max() > 1e-6 * np.abs(a).max()
+
+
+def test_weno_z_rejected_outside_1d(api):
+    import torch
+    from paper_2004_07954_amd import _lib
+    note("weno-z rejected")
+    u2, dx, dy = I.riemann_2d(1, 32)
+    with pytest.raises(_lib.WznError) as e:
+        api.rhs_2d(to_dev(u2), dx, dy, api.params("euler", weights="z"))
+    assert e.value.code == _lib.WZN_ERR_UNSUPPORTED
+    with pytest.raises(_lib.WznError) as e:
+        api.rhs_1d_char(to_dev(I.random_smooth_1d(64, seed=1)), 0.1,
+                        api.params("euler", weights="z"))
+    assert e.value.code == _lib.WZN_ERR_UNSUPPORTED
+    del torch
+
+
+# ---------------------------------------------------------------- wzn_reconstruct
+def _stencils(m, seed):
+    rng = np.random.default_rng(seed)
+    f = rng.standard_normal((5, m))
+    # degenerate rows: constant, linear, step, symmetric peak, 1e6 step
+    f[:, 0] = 2.5
+    f[:, 1] = np.arange(5) * 0.3 - 1.0
+    f[:, 2] = [0, 0, 0, 1, 1]
+    f[:, 3] = [1, 2, 3, 2, 1]
+    f[:, 4] = [0, 0, 1e6, 1e6, 1e6]
+    return f
+
+
+@pytest.mark.parametrize("weights,scheme", [("zn", 0), ("z", 1)])
+def test_reconstruct_against_oracle(api, orc, weights, scheme):
+    note("reconstruct", weights)
+    m = 3001
+    f = _stencils(m, seed=71 + scheme)
+    g = api.reconstruct(to_dev(f), api.params("euler", weights=weights)).cpu().numpy()
+    prm = orc.params(scheme=scheme, q=1)
+    r = np.array([orc.reconstruct(f[:, i], prm)["fhat"] for i in range(m)])
+    scale = np.abs(f).max(axis=0)
+    assert np.all(np.abs(g - r) <= 1e-13 * scale), np.max(np.abs(g - r) / scale)
+    assert g[0] == 2.5  # a constant is reproduced exactly
+
+
+def test_reconstruct_sizes(api):
+    import torch
+    note("reconstruct sizes")
+    out = api.reconstruct(torch.empty((5, 0), dtype=torch.float64, device="cuda"))
+    assert out.numel() == 0
+    f = _stencils(1 << 20, seed=3)
+    g = api.reconstruct(to_dev(f)).cpu().numpy()
+    assert np.isfinite(g).all()
