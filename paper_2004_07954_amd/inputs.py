@@ -54,6 +54,54 @@ def single_jump(x):
 
 
 # ------------------------------------------------------------------ 1D Euler
+# The linear advection cases of Sec. 4.2 on the periodic [-1, 1] (run to T = 6 on N = 200).
+def four_waves(x, A=1.0):
+    """Case 1 (eq:1st_case): Gaussians, square wave, triangle and half ellipse, divided by
+    the reference value A.  Constants a = 0.5, z = -0.7, delta = 0.005, alpha = 10,
+    beta = log 2 / (36 delta^2); the ellipse terms are centred at a - delta, a + delta and a."""
+    x = np.asarray(x, dtype=np.float64)
+    a, z, d, al = 0.5, -0.7, 0.005, 10.0
+    be = math.log(2.0) / (36.0 * d * d)
+
+    def G(zz):
+        return np.exp(-be * (x - zz) ** 2)
+
+    def F(aa):
+        return np.sqrt(np.maximum(1.0 - al * al * (x - aa) ** 2, 0.0))
+
+    u = np.zeros_like(x)
+    m = (x >= -0.8) & (x <= -0.6)
+    u[m] = ((G(z - d) + G(z + d) + 4.0 * G(z)) / 6.0)[m]
+    u[(x >= -0.4) & (x <= -0.2)] = 1.0
+    m = (x >= 0.0) & (x <= 0.2)
+    u[m] = (1.0 - np.abs(10.0 * (x - 0.1)))[m]
+    m = (x >= 0.4) & (x <= 0.6)
+    u[m] = ((F(a - d) + F(a + d) + 4.0 * F(a)) / 6.0)[m]
+    return u / A
+
+
+def linear_case3(x):
+    """Case 3 (eq:3rd_case)."""
+    x = np.asarray(x, dtype=np.float64)
+    return np.where(x < -1.0 / 3.0, -x * np.sin(1.5 * np.pi * x * x),
+                    np.where(x <= 1.0 / 3.0, np.abs(np.sin(2.0 * np.pi * x)),
+                             2.0 * x - 1.0 - np.sin(3.0 * np.pi * x) / 6.0))
+
+
+def linear_case(case, n, A=1.0):
+    """Cell-centre data [1, n] of linear case 1, 2 (the single jump) or 3 on [-1, 1]; dx."""
+    x, dx = cell_centres(-1.0, 1.0, n)
+    if case == 1:
+        u = four_waves(x, A)
+    elif case == 2:
+        u = single_jump(x)
+    elif case == 3:
+        u = linear_case3(x)
+    else:
+        raise ValueError("case must be 1, 2 or 3")
+    return u[None, :], dx
+
+
 def shu_osher_like(n, xl=-5.0, xr=5.0, gamma=GAMMA):
     """Left state (3.857143, 2.629369, 10.33333) for x < -4, right state
     (1 + 0.2 sin 5x, 0, 1); transmissive.  Returns (U[3, n], dx)."""
