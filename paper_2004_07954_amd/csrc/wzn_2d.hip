@@ -235,6 +235,9 @@ void col_kernel(ColArgs<T> a) {
         // the state is not needed past this point: replace it by the base of the output,
         // Lx (RHS) or fma(b_s dt, Lx, fma(a_s, U^n, b_s U)) (stage), so that the output is
         // fma(cdt, Ly, base) with cdt = 1 or b_s dt
+        // all loads of the row group are issued before any is combined (the register pins
+        // would otherwise wait for each load before issuing the next)
+        T lxv[K][4], unv[K][4];
 #pragma unroll
         for (int j = 0; j < K; ++j) {
           const int y = y0 + g * K + j;
@@ -242,12 +245,19 @@ void col_kernel(ColArgs<T> a) {
           const int64_t gi = (int64_t)(ok ? y : ys) * nx + xc;
 #pragma unroll
           for (int c = 0; c < 4; ++c) {
-            const T lx = ok ? a.lx[c * a.plane + gi] : T(0);
-            T base = lx;
+            lxv[j][c] = ok ? a.lx[c * a.plane + gi] : T(0);
+            unv[j][c] = a.mode == MODE_STAGE && a.un && ok ? a.un[c * a.plane + gi] : T(0);
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            T base = lxv[j][c];
             if (a.mode == MODE_STAGE) {
               T b = T(a.rk_b) * Ureg[j][c];
-              if (a.un) b = fma_t(T(a.rk_a), ok ? a.un[c * a.plane + gi] : T(0), b);
-              base = fma_t(cdt, lx, b);
+              if (a.un) b = fma_t(T(a.rk_a), unv[j][c], b);
+              base = fma_t(cdt, lxv[j][c], b);
             }
             Ureg[j][c] = base;
             asm volatile("" : "+v"(Ureg[j][c]));  // combine here, not in the epilogue

@@ -362,13 +362,28 @@ __device__ __forceinline__ void row_tile(const RowArgs<T>& a, int64_t g0l, int64
       }
       if (a.mode == MODE_STAGE) {
         // U is not needed past this point: replace it by the stage base a_s U^n + b_s U (the
-        // U^n read is issued here, mid-kernel, rather than in the epilogue)
+        // U^n read is issued here, mid-kernel, rather than in the epilogue).  All U^n loads
+        // are issued before any is combined: the register pins below would otherwise wait
+        // for each load before issuing the next.
+        T unv[NV][K];
+        if (a.un) {
+#pragma unroll
+          for (int c = 0; c < NV; ++c) {
+            const T* unp = a.un + c * a.plane + rowoff;
+            if (full) {
+              load_run<K, T>(unp + c0, unv[c], ((uintptr_t)(unp + g0) & 15) == 0);
+            } else {
+#pragma unroll
+              for (int j = 0; j < K; ++j) unv[c][j] = c0 + j < n ? unp[c0 + j] : T(0);
+            }
+          }
+        }
 #pragma unroll
         for (int c = 0; c < NV; ++c) {
-          const T* unp = a.un ? a.un + c * a.plane + rowoff + c0 : nullptr;
 #pragma unroll
           for (int j = 0; j < K; ++j) {
-            Ureg[j][c] = stage_base<T>(a, Ureg[j][c], unp + j, c0 + j < n);
+            const T b = T(a.rk_b) * Ureg[j][c];
+            Ureg[j][c] = a.un ? fma_t(T(a.rk_a), unv[c][j], b) : b;
             asm volatile("" : "+v"(Ureg[j][c]));  // combine here, not in the epilogue
           }
         }
