@@ -229,18 +229,6 @@ __device__ __forceinline__ void wzn_window(const float* v, float* fh, float eps_
   }
 }
 
-// Index map of the boundary conditions for a global cell index g in [-3, n + 2]
-// (and harmlessly clamped beyond): periodic wrap or transmissive copy of the edge cell.
-__device__ __forceinline__ int64_t bc_index(int64_t g, int64_t n, int bc) {
-  if (bc == 0) {  // periodic
-    if (g < 0) g += n;
-    else if (g >= n) g -= n;
-    g = g < 0 ? 0 : (g >= n ? n - 1 : g);
-    return g;
-  }
-  return g < 0 ? 0 : (g >= n ? n - 1 : g);
-}
-
 // Max of non-negative doubles through their bit patterns (order preserving; a NaN wins).
 // The slot only grows, so a plain read that already holds >= v makes the atomic unnecessary;
 // a stale read only costs an atomic that was not needed.  This keeps the number of atomics on
