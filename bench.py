@@ -248,6 +248,72 @@ def bench_char(n, steps, warmup=3, cpu_steps=3):
     return rec
 
 
+def bench_strip(evals=100):
+    """Secondary figure: one GPU's share of a row decomposition of the 4096^2 grid over eight
+    GPUs, a 4096 x 512 strip (fp64, Lax-Friedrichs), its right-hand side with ghost rows and
+    the global alphas supplied (wzn_rhs_2d_strip), against the whole-grid right-hand side on
+    this GPU.  The halo a neighbour would send per stage is 3 rows x 4096 x 4 x 8 B each way."""
+    import torch
+    from paper_2004_07954_amd import api, inputs as I
+    U, dx, dy = I.four_quadrant_random(4096, 4096, seed=3)
+    full = torch.tensor(U, dtype=torch.float64, device="cuda")
+    r0, r1 = 1536, 2048
+    strip = full[:, r0:r1].contiguous()
+    lo, hi = full[:, r0 - 3:r0].contiguous(), full[:, r1:r1 + 3].contiguous()
+    alpha2 = api.speed_max_2d(full)
+    out = torch.empty_like(strip)
+    outf = torch.empty_like(full)
+
+    def timed(fn, n):
+        fn()
+        torch.cuda.synchronize()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        for _ in range(n):
+            fn()
+        e.record()
+        torch.cuda.synchronize()
+        return s.elapsed_time(e) / n
+
+    ms_strip = timed(lambda: api.rhs_2d_strip(strip, lo, hi, dx, dy, alpha2=alpha2, out=out),
+                     evals)
+    ms_full = timed(lambda: api.rhs_2d(full, dx, dy, out=outf), max(1, evals // 8))
+    cells = 4096 * (r1 - r0)
+    return {"workload": "euler2d_strip_4096x512_of_4096x4096", "dtype": "f64",
+            "rhs_evals": evals, "ms_per_rhs": ms_strip,
+            "value": cells / (ms_strip * 1e-3), "unit": "cell-RHS/s",
+            "whole_grid_ms_per_rhs": ms_full,
+            "whole_grid_value": 4096 * 4096 / (ms_full * 1e-3),
+            "halo_bytes_per_neighbour_per_stage": 3 * 4096 * 4 * 8}
+
+
+def bench_large_1d(n=1 << 25, steps=20):
+    """Secondary figure: the 1D stage at N = 2^25 (805 MB per state, 2.4 GB in flight), where
+    the working set cannot stay in the 256 MB Infinity Cache, against the headline's 2^20."""
+    import torch
+    from paper_2004_07954_amd import api, inputs as I
+    u0, dx = I.shu_osher_like(n)
+    u = torch.tensor(u0, dtype=torch.float64, device="cuda")
+    del u0
+    stage = torch.empty((2, 3, n), dtype=torch.float64, device="cuda")
+    api.rk3_run_1d(u, dx, 2, cfl=0.5, stage=stage)
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    api.rk3_run_1d(u, dx, steps, cfl=0.5, stage=stage)
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e)
+    assert torch.isfinite(u).all().item()
+    stage_ms = ms / (3 * steps)
+    gbs = n * 64.0 / (stage_ms * 1e-3) / 1e9
+    return {"workload": "euler1d_shu_osher_like_n%d" % n, "steps": steps,
+            "value": n * 3 * steps / (ms * 1e-3), "unit": "cell-RHS/s",
+            "stage_ms": stage_ms, "hbm_gbs_algorithmic": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
+            "launch_shape": list(__import__("paper_2004_07954_amd.autotune",
+                                            fromlist=["x"]).get_row_tuning(3, n))}
+
+
 def bench_adjoint(n=65536, nsteps=400, ckpt=20, reps=3):
     """Secondary figure: the discrete adjoint of a periodic 1D Euler run (N = 65536, 400 steps,
     checkpoints every 20; loss 1/2 ||rho_T - rho_target||^2).  Reports the forward time (run
@@ -297,6 +363,9 @@ def main():
     ap.add_argument("--no-char", action="store_true",
                     help="skip the characteristic-field secondary figure")
     ap.add_argument("--steps-char", type=int, default=300)
+    ap.add_argument("--no-strip", action="store_true",
+                    help="skip the one-share-of-eight 2D strip figure")
+    ap.add_argument("--no-large", action="store_true", help="skip the 1D N = 2^25 figure")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed region, copy 256 MiB with a plain torch copy "
                          "(reference kernel for rocprof FETCH_SIZE / WRITE_SIZE scaling)")
@@ -424,6 +493,12 @@ def main():
         log("adjoint: N=65536, 400 steps")
         rec.setdefault("secondary", {})["adjoint"] = bench_adjoint()
         rec["adjoint_fwd_ratio"] = rec["secondary"]["adjoint"]["adjoint_fwd_ratio"]
+    if not args.no_strip:
+        log("2D strip 4096 x 512 (one share of eight)")
+        rec.setdefault("secondary", {})["strip"] = bench_strip()
+    if not args.no_large:
+        log("1D at N = 2^25")
+        rec.setdefault("secondary", {})["euler1d_large"] = bench_large_1d()
     if not args.no_char:
         log("characteristic fields, N =", n)
         rec.setdefault("secondary", {})["characteristic"] = bench_char(

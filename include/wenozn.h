@@ -17,8 +17,9 @@
  *
  * Conventions shared by every entry point
  *   - Every array argument is a DEVICE pointer owned by the caller; the library never
- *     allocates, frees or synchronises.  All work is enqueued on `stream` (a hipStream_t;
- *     NULL = the default stream) and is asynchronous with respect to the host.
+ *     allocates, frees or synchronises (the opt-in p->debug_nonfinite scan excepted).  All
+ *     work is enqueued on `stream` (a hipStream_t; NULL = the default stream) and is
+ *     asynchronous with respect to the host.
  *   - States are structure-of-arrays fp64: 1D [nvar][n] (nvar = 1 advection, 3 Euler:
  *     rho, rho u, E); 2D [4][ny][nx] with x fastest (rho, rho u, rho v, E).
  *     No ghost cells are stored: the boundary conditions are applied inside the kernels.
@@ -48,6 +49,7 @@ enum {
                              and batched instances <= 2^30 cells, 2D sides <= 2^24) */
   WZN_ERR_DTYPE = 3,      /* unsupported dtype for this entry point */
   WZN_ERR_HIP = 4,        /* a HIP runtime call or kernel launch failed */
+  WZN_ERR_NONFINITE = 5,  /* the output holds NaN or Inf (only with p->debug_nonfinite set) */
   WZN_ERR_UNSUPPORTED = 6 /* parameter combination not implemented on the GPU */
 };
 
@@ -79,7 +81,12 @@ typedef struct {
                            against (Sec. 2.2, eq:15), alpha_k = c_k (1 + tau5/(IS_k + eps)):
                            wzn_rhs_1d, wzn_rk3_run_1d, wzn_rk3_step_1d and wzn_reconstruct
                            only (others return WZN_ERR_UNSUPPORTED) */
-  int32_t pad;          /* unused */
+  int32_t debug_nonfinite; /* 0 (default): nothing is checked and nothing synchronises.
+                           1: a debugging aid -- every entry point with a workspace scans the
+                           array it writes (dudt, the advanced state, the cotangent) after its
+                           work, synchronises `stream`, and returns WZN_ERR_NONFINITE if any
+                           value is NaN or Inf (wzn_last_error() gives their count and one
+                           index).  The scan blocks the host; keep it off in production. */
 } wzn_params;
 
 /* Fill *p with the paper's values for `system`: A = 10, eps = 1e-40, p_C = 2, q = 1,
@@ -129,6 +136,23 @@ int32_t wzn_reconstruct(const wzn_params* p, const double* f, double* fhat, int6
  * The LF alpha is p->lf_alpha_x if >= 0, else max over cells of |u| + c (Euler) or |a|. */
 int32_t wzn_rhs_1d(const wzn_params* p, const void* u, void* dudt, int64_t n, double dx,
                    void* ws, void* stream);
+
+/* One GPU's share of a slab decomposition of a 1D Euler row.
+ * wzn_speed_max_1d: *speed1 = max over the cells of u [3][n] of |u| + c (device double): the
+ *   per-shard maximum that an all-reduce (MAX) turns into the global Lax-Friedrichs alpha
+ *   and the CFL dt (Sec. 4.3).
+ * wzn_rhs_1d_slab: dudt = L(u) for a slab of n cells of a longer row, u and dudt [3][n].  The
+ *   three cells before it come from ghost_lo and the three after it from ghost_hi ([3][3]
+ *   each, component major, in cell order: ghost_lo[c][2] is the cell just before cell 0,
+ *   ghost_hi[c][0] the cell just after cell n-1), as a neighbour would send them (or as
+ *   p->bc_x would make them at the ends of the whole row).  alpha: device pointer to the
+ *   global alpha of the whole row.  Equals the same cells of wzn_rhs_1d on the whole row bit
+ *   for bit when the ghost cells and alpha are those of the whole row. */
+int32_t wzn_speed_max_1d(const wzn_params* p, const void* u, int64_t n, double* speed1,
+                         void* ws, void* stream);
+int32_t wzn_rhs_1d_slab(const wzn_params* p, const void* u, const void* ghost_lo,
+                        const void* ghost_hi, void* dudt, int64_t n, double dx,
+                        const double* alpha, void* ws, void* stream);
 
 /* wzn_rk3_run_1d: advance u[nvar][n] in place by `nsteps` TVD-RK3 steps.
  *   stage   device scratch of 2 * nvar * n elements (the intermediate stage states).
@@ -194,6 +218,25 @@ int32_t wzn_rk3_run_1d_char(const wzn_params* p, void* u, void* stage, int64_t n
  * wzn_rhs_2d: dudt = L(u); u and dudt must not alias (dudt is also used as scratch). */
 int32_t wzn_rhs_2d(const wzn_params* p, const void* u, void* dudt, int64_t nx, int64_t ny,
                    double dx, double dy, void* ws, void* stream);
+
+/* One GPU's share of a row decomposition of the 2D grid.
+ * wzn_speed_max_2d: speed2[0] = max over the cells of u [4][ny][nx] of |u| + c, speed2[1] =
+ *   max of |v| + c (device doubles): the per-shard maxima that an all-reduce (MAX) over the
+ *   shards turns into the global alphas of the Lax-Friedrichs split (Sec. 4.4) and the CFL dt.
+ * wzn_rhs_2d_strip: dudt = L(u) for a strip of ny rows of a larger grid (u, dudt:
+ *   [4][ny][nx]).  The y sweep takes the three rows below the strip from ghost_lo and the three
+ *   above from ghost_hi ([4][3][nx] each, nearest row last / first: ghost_lo row 2 is the row
+ *   just below row 0, ghost_hi row 0 the row just above row ny-1), as a neighbour would send
+ *   them (or as p->bc_y would make them at the edge of the whole grid); p->bc_x applies in x.
+ *   alpha2: device [2], the global (alpha_x, alpha_y) of the whole grid (required for the
+ *   Lax-Friedrichs split, unused by Steger-Warming).  The rows of a strip equal the same rows
+ *   of wzn_rhs_2d on the whole grid bit for bit when the ghost rows and alphas are those of
+ *   the whole grid.  ny >= 6; u and dudt must not alias (dudt is also scratch). */
+int32_t wzn_speed_max_2d(const wzn_params* p, const void* u, int64_t nx, int64_t ny,
+                         double* speed2, void* ws, void* stream);
+int32_t wzn_rhs_2d_strip(const wzn_params* p, const void* u, const void* ghost_lo,
+                         const void* ghost_hi, void* dudt, int64_t nx, int64_t ny, double dx,
+                         double dy, const double* alpha2, void* ws, void* stream);
 
 /* wzn_rk3_run_2d: advance u in place by `nsteps` TVD-RK3 steps.
  *   stage  device scratch of 2 * 4 * nx * ny elements of the dtype.

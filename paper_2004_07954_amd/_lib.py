@@ -11,6 +11,7 @@ LIB_PATH = os.path.join(HERE, "libwenozn.so")
 
 WZN_ABI_VERSION = 2
 WZN_OK, WZN_ERR_ARG, WZN_ERR_SIZE, WZN_ERR_DTYPE, WZN_ERR_HIP = 0, 1, 2, 3, 4
+WZN_ERR_NONFINITE = 5
 WZN_ERR_UNSUPPORTED = 6
 WZN_ADVECTION, WZN_EULER = 0, 1
 WZN_FP64, WZN_FP32 = 0, 1
@@ -24,7 +25,7 @@ class WznParams(C.Structure):
                 ("bc_x", C.c_int32), ("bc_y", C.c_int32), ("p_C", C.c_int32), ("q", C.c_int32),
                 ("flux_split", C.c_int32), ("adv_speed", C.c_double), ("gamma", C.c_double),
                 ("A", C.c_double), ("eps", C.c_double), ("lf_alpha_x", C.c_double),
-                ("lf_alpha_y", C.c_double), ("weights", C.c_int32), ("pad", C.c_int32)]
+                ("lf_alpha_y", C.c_double), ("weights", C.c_int32), ("debug_nonfinite", C.c_int32)]
 
 
 class WznBatchTuning(C.Structure):
@@ -46,11 +47,15 @@ SIGNATURES = [
     ("wzn_workspace_bytes", _SZ, [_PP, _I64, _I64]),
     ("wzn_reconstruct", _I32, [_PP, _P, _P, _I64, _P]),
     ("wzn_rhs_1d", _I32, [_PP, _P, _P, _I64, _D, _P, _P]),
+    ("wzn_speed_max_1d", _I32, [_PP, _P, _I64, _P, _P, _P]),
+    ("wzn_rhs_1d_slab", _I32, [_PP, _P, _P, _P, _P, _I64, _D, _P, _P, _P]),
     ("wzn_rk3_run_1d", _I32, [_PP, _P, _P, _I64, _D, _D, _I32, _P, _P, _P, _P, _P, _P]),
     ("wzn_rk3_step_1d", _I32, [_PP, _P, _P, _I64, _D, _D, _P, _P, _P, _P]),
     ("wzn_rhs_1d_char", _I32, [_PP, _P, _P, _I64, _D, _P, _P, _P]),
     ("wzn_rk3_run_1d_char", _I32, [_PP, _P, _P, _I64, _D, _D, _I32, _P, _P, _P, _P, _P, _P]),
     ("wzn_rhs_2d", _I32, [_PP, _P, _P, _I64, _I64, _D, _D, _P, _P]),
+    ("wzn_speed_max_2d", _I32, [_PP, _P, _I64, _I64, _P, _P, _P]),
+    ("wzn_rhs_2d_strip", _I32, [_PP, _P, _P, _P, _P, _I64, _I64, _D, _D, _P, _P, _P]),
     ("wzn_rk3_run_2d", _I32, [_PP, _P, _P, _I64, _I64, _D, _D, _D, _I32, _P, _P, _P, _P]),
     ("wzn_rk3_step_2d", _I32, [_PP, _P, _P, _I64, _I64, _D, _D, _D, _P, _P, _P, _P]),
     ("wzn_batched_rk3_run_1d", _I32, [_PP, _P, _P, _I64, _P, _P, _P, _I32, _I32, _D,

@@ -18,10 +18,12 @@ WEIGHTS = {"zn": _lib.WZN_WEIGHTS_ZN, "z": _lib.WZN_WEIGHTS_Z}
 
 
 def params(system="euler", bc="transmissive", bc_y=None, adv_speed=1.0, gamma=1.4, A=10.0,
-           eps=1e-40, lf_alpha=None, lf_alpha_y=None, dtype="fp64", split="lf", weights="zn"):
+           eps=1e-40, lf_alpha=None, lf_alpha_y=None, dtype="fp64", split="lf", weights="zn",
+           debug_nonfinite=False):
     """WENO-ZN parameters; defaults are the paper's (A = 10, eps = 1e-40, gamma = 1.4).
     split: "lf" (global Lax-Friedrichs) or "sw" (Steger-Warming, 2D only); weights: "zn"
-    (the paper's) or "z" (WENO-Z, q = 1, the comparison scheme; 1D and reconstruct only)."""
+    (the paper's) or "z" (WENO-Z, q = 1, the comparison scheme; 1D and reconstruct only);
+    debug_nonfinite: scan every output for NaN / Inf and raise (synchronises; debugging only)."""
     p = WznParams()
     lib().wzn_default_params(C.byref(p), SYSTEMS[system])
     p.bc_x = BCS[bc]
@@ -35,6 +37,7 @@ def params(system="euler", bc="transmissive", bc_y=None, adv_speed=1.0, gamma=1.
     p.dtype = {"fp64": _lib.WZN_FP64, "fp32": _lib.WZN_FP32}[dtype]
     p.flux_split = SPLITS[split]
     p.weights = WEIGHTS[weights]
+    p.debug_nonfinite = 1 if debug_nonfinite else 0
     return p
 
 
@@ -83,7 +86,10 @@ def _dev_f64(x, n, name, device):
         return None
     if not isinstance(x, torch.Tensor):
         x = torch.as_tensor(x, dtype=torch.float64)
-    x = x.to(device=device, dtype=torch.float64).reshape(-1).contiguous()
+    elif x.dtype != torch.float64:
+        # a float32 tensor would silently round the value (dt, alpha) it carries
+        raise TypeError("%s must be float64, got %s" % (name, x.dtype))
+    x = x.to(device=device).reshape(-1).contiguous()
     if x.numel() != n:
         raise ValueError("%s must have %d entries" % (name, n))
     return x
@@ -112,6 +118,34 @@ def rhs_1d(u, dx, prm=None, out=None):
     _check_state(out, _nv(prm), "out")
     check(lib().wzn_rhs_1d(C.byref(prm), _ptr(u), _ptr(out), u.shape[1], float(dx),
                            _ptr(workspace(u.device)), _stream()))
+    return out
+
+
+def speed_max_1d(u, prm=None, out=None):
+    """Device tensor [1]: max(|u| + c) over the cells of 1D Euler u [3, n]."""
+    prm = prm or params()
+    _check_state(u, 3)
+    out = torch.empty(1, dtype=torch.float64, device=u.device) if out is None else out
+    check(lib().wzn_speed_max_1d(C.byref(prm), _ptr(u), u.shape[1], _ptr(out),
+                                 _ptr(workspace(u.device)), _stream()))
+    return out
+
+
+def rhs_1d_slab(u, ghost_lo, ghost_hi, dx, alpha, prm=None, out=None):
+    """L(u) for a slab u [3, n] of a longer 1D Euler row with ghost cells ghost_lo / ghost_hi
+    [3, 3] (the three cells before / after it) and the global alpha of the whole row."""
+    prm = prm or params()
+    _check_state(u, 3)
+    for g, name in ((ghost_lo, "ghost_lo"), (ghost_hi, "ghost_hi")):
+        if (not isinstance(g, torch.Tensor) or g.dtype != torch.float64 or g.device != u.device
+                or not g.is_contiguous() or tuple(g.shape) != (3, 3)):
+            raise ValueError("%s must be a contiguous float64 [3, 3] tensor on u's device" % name)
+    al = _dev_f64(alpha, 1, "alpha", u.device)
+    out = torch.empty_like(u) if out is None else out
+    _check_state(out, 3, "out")
+    check(lib().wzn_rhs_1d_slab(C.byref(prm), _ptr(u), _ptr(ghost_lo), _ptr(ghost_hi),
+                                _ptr(out), u.shape[1], float(dx), _ptr(al),
+                                _ptr(workspace(u.device)), _stream()))
     return out
 
 
@@ -232,6 +266,36 @@ def rhs_2d(u, dx, dy, prm=None, out=None):
     _check_state_2d(out, "out")
     check(lib().wzn_rhs_2d(C.byref(prm), _ptr(u), _ptr(out), u.shape[2], u.shape[1], float(dx),
                            float(dy), _ptr(workspace(u.device)), _stream()))
+    return out
+
+
+def speed_max_2d(u, prm=None, out=None):
+    """Device tensor [2]: max(|u| + c), max(|v| + c) over the cells of u [4, ny, nx]."""
+    prm = _params_2d(prm, u)
+    _check_state_2d(u)
+    out = torch.empty(2, dtype=torch.float64, device=u.device) if out is None else out
+    check(lib().wzn_speed_max_2d(C.byref(prm), _ptr(u), u.shape[2], u.shape[1], _ptr(out),
+                                 _ptr(workspace(u.device)), _stream()))
+    return out
+
+
+def rhs_2d_strip(u, ghost_lo, ghost_hi, dx, dy, alpha2=None, prm=None, out=None):
+    """L(u) for a strip u [4, ny, nx] of a larger grid with ghost rows ghost_lo / ghost_hi
+    [4, 3, nx] (the three rows below / above it) and the global alphas alpha2 = (alpha_x,
+    alpha_y) of the whole grid (device tensor or sequence; Lax-Friedrichs only)."""
+    prm = _params_2d(prm, u)
+    _check_state_2d(u)
+    nx = u.shape[2]
+    for g, name in ((ghost_lo, "ghost_lo"), (ghost_hi, "ghost_hi")):
+        if (not isinstance(g, torch.Tensor) or g.dtype != u.dtype or g.device != u.device
+                or not g.is_contiguous() or tuple(g.shape) != (4, 3, nx)):
+            raise ValueError("%s must be a contiguous [4, 3, nx] tensor like u" % name)
+    al = _dev_f64(alpha2, 2, "alpha2", u.device)
+    out = torch.empty_like(u) if out is None else out
+    _check_state_2d(out, "out")
+    check(lib().wzn_rhs_2d_strip(C.byref(prm), _ptr(u), _ptr(ghost_lo), _ptr(ghost_hi),
+                                 _ptr(out), nx, u.shape[1], float(dx), float(dy), _ptr(al),
+                                 _ptr(workspace(u.device)), _stream()))
     return out
 
 

@@ -116,6 +116,38 @@ int rhs_1d(const wzn_params* p, const double* u, double* dudt, int64_t n, double
   return launch_rows(a, sys_of(p), 1, tuning_1d(nv, n), s);
 }
 
+// Right-hand side of a slab of n cells of a longer 1D Euler row (one GPU's share of a slab
+// decomposition): its three cells on each side from ghost_lo / ghost_hi ([3][3], component
+// major), and the caller's alpha (the maximum over the whole row: a per-slab alpha would change
+// the scheme).
+int rhs_1d_slab(const wzn_params* p, const double* u, const double* ghost_lo,
+                const double* ghost_hi, double* dudt, int64_t n, double dx, const double* alpha,
+                hipStream_t s) {
+  RowArgs<double> a = base_args(p, n, dx);
+  a.uin = u;
+  a.out = dudt;
+  a.mode = MODE_RHS;
+  a.alpha_arr = alpha;
+  a.ghost_lo = ghost_lo;
+  a.ghost_hi = ghost_hi;
+  return launch_rows(a, SYS_EULER1, 1, tuning_1d(3, n), s);
+}
+
+// max over the cells of u [3][n] of |u| + c into *out (device double)
+__global__ void slot_to_double_kernel(const unsigned long long* slot, double* out) {
+  if (threadIdx.x == 0) out[0] = slot_value(slot);
+}
+
+int speed_max_1d(const wzn_params* p, const double* u, int64_t n, double* out, Workspace* ws,
+                 hipStream_t s) {
+  int st = launch_zero_words(ws->speed, 1, s);
+  if (st) return st;
+  st = launch_speed_max<double>(u, n, 3, p->gamma, ws->speed, nullptr, s);
+  if (st) return st;
+  hipLaunchKernelGGL(slot_to_double_kernel, dim3(1), dim3(64), 0, s, ws->speed, out);
+  return check_launch("slot_to_double_kernel");
+}
+
 // One reconstruction per thread from five point values (structure of arrays [5][m]).  The
 // window carries its indicators scaled by 4, so eps enters as 4 eps (see wzn_device.hpp).
 template <int WT>
@@ -142,6 +174,50 @@ int reconstruct(const wzn_params* p, const double* f, double* fhat, int64_t m, h
     hipLaunchKernelGGL((reconstruct_kernel<WEIGHTS_ZN>), dim3((unsigned)blocks), dim3(256), 0, s,
                        f, fhat, m, 4.0 * p->eps, 0.25 * p->A);
   return check_launch("reconstruct_kernel");
+}
+
+// Count of non-finite values of x[0 .. count) into flag[0] and the largest index + 1 of one into
+// flag[1] (both zero beforehand).
+template <typename T>
+__global__ __launch_bounds__(256) void nonfinite_scan_kernel(const T* __restrict__ x, int64_t count,
+                                                             unsigned long long* flag) {
+  unsigned long long bad = 0, last = 0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * 256) {
+    if (!__builtin_isfinite(double(x[i]))) {
+      ++bad;
+      last = (unsigned long long)i + 1;
+    }
+  }
+  if (bad) {
+    atomicAdd(&flag[0], bad);
+    atomicMax(&flag[1], last);
+  }
+}
+
+int debug_nonfinite_scan(const void* x, int64_t count, bool f32, Workspace* ws, hipStream_t s) {
+  unsigned long long* flag = ws->scratch;
+  int st = launch_zero_words(flag, 2, s);
+  if (st) return st;
+  int64_t blocks = (count + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  if (f32)
+    hipLaunchKernelGGL((nonfinite_scan_kernel<float>), dim3((unsigned)blocks), dim3(256), 0, s,
+                       (const float*)x, count, flag);
+  else
+    hipLaunchKernelGGL((nonfinite_scan_kernel<double>), dim3((unsigned)blocks), dim3(256), 0, s,
+                       (const double*)x, count, flag);
+  st = check_launch("nonfinite_scan_kernel");
+  if (st) return st;
+  unsigned long long host[2] = {0, 0};
+  if (hipMemcpyAsync(host, flag, sizeof(host), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return set_error(WZN_ERR_HIP, "debug scan: copy of the flag failed");
+  if (host[0])
+    return set_error(WZN_ERR_NONFINITE, "%llu non-finite output values (one at element %lld)",
+                     host[0], (long long)host[1] - 1);
+  return WZN_OK;
 }
 
 static const double RK_A[3] = {0.0, 3.0 / 4.0, 1.0 / 3.0};

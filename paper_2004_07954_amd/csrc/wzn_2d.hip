@@ -53,6 +53,10 @@ struct ColArgs {
   unsigned long long* speed_next_y;
   unsigned long long* zero_x;
   unsigned long long* zero_y;
+  // strip of a larger grid (one GPU's share): the three rows below and above it come from
+  // these [4][3][nx] arrays (rows -3..-1 and ny..ny+2) instead of the boundary condition
+  const T* ghost_lo;
+  const T* ghost_hi;
 };
 
 // Column tile: NG row groups (one 64-lane wave each) of K rows, 64 columns; TY = NG*K rows per
@@ -77,6 +81,30 @@ __device__ __forceinline__ void flux_y(const T (&U)[4], T (&G)[4], T gm1) {
   G[3] = v * (U[3] + p);
 }
 
+// The state of row y in [-3, ny + 2] (rows past ny + 2 only feed interfaces of rows that are
+// not stored) at column xc: the boundary condition's index map, or (GHOST) the caller's ghost
+// rows below and above a strip.
+template <bool GHOST, typename T>
+__device__ __forceinline__ void col_state(const ColArgs<T>& a, int y, int ny, int nx, int xc,
+                                          T (&U)[4]) {
+  if constexpr (GHOST) {
+    if (y < 0 || y >= ny) {
+      const T* gsrc = y < 0 ? a.ghost_lo : a.ghost_hi;
+      const int r = y < 0 ? y + 3 : min(y - ny, 2);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) U[c] = gsrc[((int64_t)c * 3 + r) * nx + xc];
+      return;
+    }
+    const int64_t gi = (int64_t)y * nx + xc;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) U[c] = a.uin[c * a.plane + gi];
+  } else {
+    const int64_t gi = (int64_t)bc_cell(y, ny, a.bc) * nx + xc;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) U[c] = a.uin[c * a.plane + gi];
+  }
+}
+
 // One workgroup walks down the rows [y_s, y_e) of a strip of 64 columns, TY rows per iteration.
 // Thread (column, group g) loads, reconstructs and finishes rows y0 + gK .. y0 + gK + K - 1 of
 // its column; the split fluxes of all components are staged one sign at a time (w^+ first,
@@ -85,7 +113,7 @@ __device__ __forceinline__ void flux_y(const T (&U)[4], T (&G)[4], T gm1) {
 // LDS), or at the segment's first row the boundary interface, reconstructed once per segment.
 // Four waves per SIMD (128 VGPRs; the fp64 variant with the wave-speed epilogue spills a few
 // bytes, which costs far less than dropping to three waves).
-template <int NG, int K, typename T, bool SPEED, bool SW>
+template <int NG, int K, typename T, bool SPEED, bool SW, bool GHOST>
 __global__ __launch_bounds__(64 * NG) __attribute__((amdgpu_waves_per_eu(4)))
 void col_kernel(ColArgs<T> a) {
   static_assert(NG >= 4, "the segment's boundary interface uses one group per component");
@@ -147,12 +175,7 @@ void col_kernel(ColArgs<T> a) {
       __syncthreads();  // W, XF and CARRY of the previous phase / iteration are consumed
       if (ph == 0) {
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
-          const int yy = bc_cell(y0 + g * K + j, ny, a.bc);
-          const int64_t gi = (int64_t)yy * nx + xc;
-#pragma unroll
-          for (int c = 0; c < 4; ++c) Ureg[j][c] = a.uin[c * a.plane + gi];
-        }
+        for (int j = 0; j < K; ++j) col_state<GHOST, T>(a, y0 + g * K + j, ny, nx, xc, Ureg[j]);
 #pragma unroll
         for (int j = 0; j < K; ++j) {
           T G[4];
@@ -171,10 +194,7 @@ void col_kernel(ColArgs<T> a) {
 #pragma unroll
           for (int hh = 0; hh < 2; ++hh) {
             const int p = hh == 0 ? g : TY + 3 + g;
-            const int yy = bc_cell(y0 + p - 3, ny, a.bc);
-            const int64_t gi = (int64_t)yy * nx + xc;
-#pragma unroll
-            for (int c = 0; c < 4; ++c) HU[hh][c] = a.uin[c * a.plane + gi];
+            col_state<GHOST, T>(a, y0 + p - 3, ny, nx, xc, HU[hh]);
             T G[4];
             if constexpr (SW) {
               // (the second phase re-reads the halo state rather than holding it)
@@ -213,10 +233,7 @@ void col_kernel(ColArgs<T> a) {
             const int p = hh == 0 ? g : TY + 3 + g;
             if constexpr (SW) {
               T Uh[4], G[4];
-              const int yy = bc_cell(y0 + p - 3, ny, a.bc);
-              const int64_t gi = (int64_t)yy * nx + xc;
-#pragma unroll
-              for (int c = 0; c < 4; ++c) Uh[c] = a.uin[c * a.plane + gi];
+              col_state<GHOST, T>(a, y0 + p - 3, ny, nx, xc, Uh);
               sw_flux2<1, true, T>(Uh, G, gm1, gam, inv_gam, inv_gm1);
 #pragma unroll
               for (int c = 0; c < 4; ++c) W[(c * NPOS + p) * 64 + col] = G[c];
@@ -373,12 +390,21 @@ static int launch_col_t(ColArgs<T> a, hipStream_t s) {
   a.seg = (int)seg;
   if (bx > 0x7fffffff || nseg > 65535) return set_error(WZN_ERR_SIZE, "grid too large (columns)");
   const dim3 grid((unsigned)bx, (unsigned)nseg), block(64 * NG);
-  if (a.split == SPLIT_SW) {
-    if (a.speed_next_x) hipLaunchKernelGGL((col_kernel<NG, K, T, true, true>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((col_kernel<NG, K, T, false, true>), grid, block, 0, s, a);
+  if (a.ghost_lo) {  // strip right-hand side: no stage epilogue
+    if (a.split == SPLIT_SW)
+      hipLaunchKernelGGL((col_kernel<NG, K, T, false, true, true>), grid, block, 0, s, a);
+    else
+      hipLaunchKernelGGL((col_kernel<NG, K, T, false, false, true>), grid, block, 0, s, a);
+  } else if (a.split == SPLIT_SW) {
+    if (a.speed_next_x)
+      hipLaunchKernelGGL((col_kernel<NG, K, T, true, true, false>), grid, block, 0, s, a);
+    else
+      hipLaunchKernelGGL((col_kernel<NG, K, T, false, true, false>), grid, block, 0, s, a);
   } else {
-    if (a.speed_next_x) hipLaunchKernelGGL((col_kernel<NG, K, T, true, false>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((col_kernel<NG, K, T, false, false>), grid, block, 0, s, a);
+    if (a.speed_next_x)
+      hipLaunchKernelGGL((col_kernel<NG, K, T, true, false, false>), grid, block, 0, s, a);
+    else
+      hipLaunchKernelGGL((col_kernel<NG, K, T, false, false, false>), grid, block, 0, s, a);
   }
   return check_launch("col_kernel");
 }
@@ -467,6 +493,62 @@ int rhs_2d_t(const wzn_params* p, const T* u, T* dudt, int64_t nx, int64_t ny, d
 }
 template int rhs_2d_t<double>(const wzn_params*, const double*, double*, int64_t, int64_t, double,
                               double, Workspace*, hipStream_t);
+
+// Right-hand side of a strip of ny rows of a larger grid (one GPU's share of a row
+// decomposition): the y sweep takes its three rows below and above from ghost_lo / ghost_hi,
+// and both sweeps use the caller's alphas (the maxima over the whole grid: a per-strip alpha
+// would change the scheme).  The x sweep needs no halo from other strips.
+template <typename T>
+int rhs_2d_strip_t(const wzn_params* p, const T* u, const T* ghost_lo, const T* ghost_hi,
+                   T* dudt, int64_t nx, int64_t ny, double dx, double dy, const double* alpha2,
+                   hipStream_t s) {
+  RowArgs<T> ra = row_args<T>(p, nx, ny, dx);
+  ColArgs<T> ca = col_args<T>(p, nx, ny, dx, dy);
+  ra.alpha_arr = alpha2;
+  ca.alpha_arr = alpha2 ? alpha2 + 1 : nullptr;
+  ra.uin = u;
+  ra.out = dudt;
+  int st = launch_rows(ra, SYS_EULER2X, ny, tuning_2dx(), s);
+  if (st) return st;
+  ca.uin = u;
+  ca.lx = dudt;
+  ca.out = dudt;
+  ca.mode = MODE_RHS;
+  ca.ghost_lo = ghost_lo;
+  ca.ghost_hi = ghost_hi;
+  return launch_col_t<ColShape<T>::NG, ColShape<T>::K, T>(ca, s);
+}
+template int rhs_2d_strip_t<double>(const wzn_params*, const double*, const double*, const double*,
+                                    double*, int64_t, int64_t, double, double, const double*,
+                                    hipStream_t);
+template int rhs_2d_strip_t<float>(const wzn_params*, const float*, const float*, const float*,
+                                   float*, int64_t, int64_t, double, double, const double*,
+                                   hipStream_t);
+
+__global__ void slots_to_doubles_kernel(const unsigned long long* sx,
+                                        const unsigned long long* sy, double* out) {
+  if (threadIdx.x == 0) {
+    out[0] = slot_value(sx);
+    out[1] = slot_value(sy);
+  }
+}
+
+// max over the cells of u of |u| + c and |v| + c into out[0], out[1] (device doubles)
+template <typename T>
+int speed_max_2d_t(const wzn_params* p, const T* u, int64_t nx, int64_t ny, double* out,
+                   Workspace* ws, hipStream_t s) {
+  int st = launch_zero_words(ws->speed, 6, s);
+  if (st) return st;
+  st = launch_speed_max<T>(u, nx * ny, 4, p->gamma, &ws->speed[0], &ws->speed_y[0], s);
+  if (st) return st;
+  hipLaunchKernelGGL(slots_to_doubles_kernel, dim3(1), dim3(64), 0, s, &ws->speed[0],
+                     &ws->speed_y[0], out);
+  return check_launch("slots_to_doubles_kernel");
+}
+template int speed_max_2d_t<double>(const wzn_params*, const double*, int64_t, int64_t, double*,
+                                    Workspace*, hipStream_t);
+template int speed_max_2d_t<float>(const wzn_params*, const float*, int64_t, int64_t, double*,
+                                   Workspace*, hipStream_t);
 template int rhs_2d_t<float>(const wzn_params*, const float*, float*, int64_t, int64_t, double,
                              double, Workspace*, hipStream_t);
 

@@ -67,6 +67,8 @@ static int check_params(const wzn_params* p, bool allow_fp32, bool allow_z = fal
     return set_error(WZN_ERR_ARG, "unknown flux_split %d", p->flux_split);
   if (p->weights != WZN_WEIGHTS_ZN && p->weights != WZN_WEIGHTS_Z)
     return set_error(WZN_ERR_ARG, "unknown weights %d", p->weights);
+  if (p->debug_nonfinite != 0 && p->debug_nonfinite != 1)
+    return set_error(WZN_ERR_ARG, "debug_nonfinite must be 0 or 1");
   if (p->weights == WZN_WEIGHTS_Z && !allow_z)
     return set_error(WZN_ERR_UNSUPPORTED,
                      "the WENO-Z weights run in wzn_rhs_1d, wzn_rk3_run_1d and wzn_reconstruct");
@@ -77,6 +79,13 @@ static int check_params(const wzn_params* p, bool allow_fp32, bool allow_z = fal
   if (p->system == WZN_ADVECTION && !(p->adv_speed != 0.0) && p->lf_alpha_x < 0.0)
     return set_error(WZN_ERR_ARG, "advection speed must be nonzero");
   return WZN_OK;
+}
+
+// The debug_nonfinite mode: after an entry point's work, scan the array it wrote.
+static int scanned(int st, const wzn_params* p, const void* x, int64_t count, bool f32,
+                   Workspace* w, void* stream) {
+  if (st || !p->debug_nonfinite) return st;
+  return debug_nonfinite_scan(x, count, f32, w, (hipStream_t)stream);
 }
 
 static int check_1d(const wzn_params* p, int64_t n, double dx, void* ws, bool allow_z = false) {
@@ -142,6 +151,7 @@ const char* wzn_status_string(int32_t status) {
     case WZN_ERR_SIZE: return "invalid size";
     case WZN_ERR_DTYPE: return "unsupported dtype";
     case WZN_ERR_HIP: return "HIP error";
+    case WZN_ERR_NONFINITE: return "non-finite output";
     case WZN_ERR_UNSUPPORTED: return "unsupported parameters";
     default: return "unknown status";
   }
@@ -205,7 +215,37 @@ int32_t wzn_rhs_1d(const wzn_params* p, const void* u, void* dudt, int64_t n, do
   if (!u || !dudt) return set_error(WZN_ERR_ARG, "u or dudt is NULL");
   if (u == dudt) return set_error(WZN_ERR_ARG, "u and dudt must not alias");
   Workspace w = make_workspace(ws);
-  return rhs_1d(p, (const double*)u, (double*)dudt, n, dx, &w, (hipStream_t)stream);
+  const int64_t nv = p->system == WZN_EULER ? 3 : 1;
+  return scanned(rhs_1d(p, (const double*)u, (double*)dudt, n, dx, &w, (hipStream_t)stream), p,
+                 dudt, nv * n, false, &w, stream);
+}
+
+int32_t wzn_speed_max_1d(const wzn_params* p, const void* u, int64_t n, double* speed1,
+                         void* ws, void* stream) {
+  g_err[0] = 0;
+  int st = check_1d(p, n, 1.0, ws);
+  if (st) return st;
+  if (p->system != WZN_EULER) return set_error(WZN_ERR_ARG, "1D Euler only");
+  if (!u || !speed1) return set_error(WZN_ERR_ARG, "NULL array argument");
+  Workspace w = make_workspace(ws);
+  return speed_max_1d(p, (const double*)u, n, speed1, &w, (hipStream_t)stream);
+}
+
+int32_t wzn_rhs_1d_slab(const wzn_params* p, const void* u, const void* ghost_lo,
+                        const void* ghost_hi, void* dudt, int64_t n, double dx,
+                        const double* alpha, void* ws, void* stream) {
+  g_err[0] = 0;
+  int st = check_1d(p, n, dx, ws);
+  if (st) return st;
+  if (p->system != WZN_EULER) return set_error(WZN_ERR_ARG, "slabs are for 1D Euler");
+  if (!u || !ghost_lo || !ghost_hi || !dudt || !alpha)
+    return set_error(WZN_ERR_ARG, "NULL argument");
+  if (u == dudt) return set_error(WZN_ERR_ARG, "u and dudt must not alias");
+  Workspace w = make_workspace(ws);
+  return scanned(rhs_1d_slab(p, (const double*)u, (const double*)ghost_lo,
+                             (const double*)ghost_hi, (double*)dudt, n, dx, alpha,
+                             (hipStream_t)stream),
+                 p, dudt, 3 * n, false, &w, stream);
 }
 
 int32_t wzn_rk3_run_1d(const wzn_params* p, void* u, void* stage, int64_t n, double dx,
@@ -218,8 +258,10 @@ int32_t wzn_rk3_run_1d(const wzn_params* p, void* u, void* stage, int64_t n, dou
   if (nsteps < 0) return set_error(WZN_ERR_ARG, "nsteps < 0");
   if (!dt_in && !(cfl > 0.0)) return set_error(WZN_ERR_ARG, "cfl must be positive");
   Workspace w = make_workspace(ws);
-  return rk3_run_1d(p, (double*)u, (double*)stage, n, dx, cfl, nsteps, dt_in, alpha_in, dt_out,
-                    alpha_out, &w, (hipStream_t)stream);
+  const int64_t nv = p->system == WZN_EULER ? 3 : 1;
+  return scanned(rk3_run_1d(p, (double*)u, (double*)stage, n, dx, cfl, nsteps, dt_in, alpha_in,
+                            dt_out, alpha_out, &w, (hipStream_t)stream),
+                 p, u, nv * n, false, &w, stream);
 }
 
 int32_t wzn_rk3_step_1d(const wzn_params* p, void* u, void* stage, int64_t n, double dx,
@@ -238,7 +280,9 @@ int32_t wzn_rhs_1d_char(const wzn_params* p, const void* u, void* dudt, int64_t 
   if (!u || !dudt) return set_error(WZN_ERR_ARG, "u or dudt is NULL");
   if (u == dudt) return set_error(WZN_ERR_ARG, "u and dudt must not alias");
   Workspace w = make_workspace(ws);
-  return rhs_1d_char(p, (const double*)u, (double*)dudt, n, dx, alpha3, &w, (hipStream_t)stream);
+  return scanned(rhs_1d_char(p, (const double*)u, (double*)dudt, n, dx, alpha3, &w,
+                             (hipStream_t)stream),
+                 p, dudt, 3 * n, false, &w, stream);
 }
 
 int32_t wzn_rk3_run_1d_char(const wzn_params* p, void* u, void* stage, int64_t n, double dx,
@@ -254,8 +298,9 @@ int32_t wzn_rk3_run_1d_char(const wzn_params* p, void* u, void* stage, int64_t n
   if (nsteps < 0) return set_error(WZN_ERR_ARG, "nsteps < 0");
   if (!dt_in && !(cfl > 0.0)) return set_error(WZN_ERR_ARG, "cfl must be positive");
   Workspace w = make_workspace(ws);
-  return rk3_run_1d_char(p, (double*)u, (double*)stage, n, dx, cfl, nsteps, dt_in, alpha_in,
-                         dt_out, alpha_out, &w, (hipStream_t)stream);
+  return scanned(rk3_run_1d_char(p, (double*)u, (double*)stage, n, dx, cfl, nsteps, dt_in,
+                                 alpha_in, dt_out, alpha_out, &w, (hipStream_t)stream),
+                 p, u, 3 * n, false, &w, stream);
 }
 
 int32_t wzn_rhs_2d(const wzn_params* p, const void* u, void* dudt, int64_t nx, int64_t ny,
@@ -266,11 +311,46 @@ int32_t wzn_rhs_2d(const wzn_params* p, const void* u, void* dudt, int64_t nx, i
   if (!u || !dudt) return set_error(WZN_ERR_ARG, "u or dudt is NULL");
   if (u == dudt) return set_error(WZN_ERR_ARG, "u and dudt must not alias");
   Workspace w = make_workspace(ws);
+  const bool f32 = p->dtype == WZN_FP32;
+  st = f32 ? rhs_2d_t<float>(p, (const float*)u, (float*)dudt, nx, ny, dx, dy, &w,
+                             (hipStream_t)stream)
+           : rhs_2d_t<double>(p, (const double*)u, (double*)dudt, nx, ny, dx, dy, &w,
+                              (hipStream_t)stream);
+  return scanned(st, p, dudt, 4 * nx * ny, f32, &w, stream);
+}
+
+int32_t wzn_rhs_2d_strip(const wzn_params* p, const void* u, const void* ghost_lo,
+                         const void* ghost_hi, void* dudt, int64_t nx, int64_t ny, double dx,
+                         double dy, const double* alpha2, void* ws, void* stream) {
+  g_err[0] = 0;
+  int st = check_2d(p, nx, ny, dx, dy, ws);
+  if (st) return st;
+  if (!u || !ghost_lo || !ghost_hi || !dudt)
+    return set_error(WZN_ERR_ARG, "NULL array argument");
+  if (u == dudt) return set_error(WZN_ERR_ARG, "u and dudt must not alias");
+  if (p->flux_split == WZN_SPLIT_LF && !alpha2)
+    return set_error(WZN_ERR_ARG, "the Lax-Friedrichs split of a strip needs the global alphas");
+  Workspace w = make_workspace(ws);
+  const bool f32 = p->dtype == WZN_FP32;
+  st = f32 ? rhs_2d_strip_t<float>(p, (const float*)u, (const float*)ghost_lo,
+                                   (const float*)ghost_hi, (float*)dudt, nx, ny, dx, dy, alpha2,
+                                   (hipStream_t)stream)
+           : rhs_2d_strip_t<double>(p, (const double*)u, (const double*)ghost_lo,
+                                    (const double*)ghost_hi, (double*)dudt, nx, ny, dx, dy,
+                                    alpha2, (hipStream_t)stream);
+  return scanned(st, p, dudt, 4 * nx * ny, f32, &w, stream);
+}
+
+int32_t wzn_speed_max_2d(const wzn_params* p, const void* u, int64_t nx, int64_t ny,
+                         double* speed2, void* ws, void* stream) {
+  g_err[0] = 0;
+  int st = check_2d(p, nx, ny, 1.0, 1.0, ws);
+  if (st) return st;
+  if (!u || !speed2) return set_error(WZN_ERR_ARG, "NULL array argument");
+  Workspace w = make_workspace(ws);
   if (p->dtype == WZN_FP32)
-    return rhs_2d_t<float>(p, (const float*)u, (float*)dudt, nx, ny, dx, dy, &w,
-                           (hipStream_t)stream);
-  return rhs_2d_t<double>(p, (const double*)u, (double*)dudt, nx, ny, dx, dy, &w,
-                          (hipStream_t)stream);
+    return speed_max_2d_t<float>(p, (const float*)u, nx, ny, speed2, &w, (hipStream_t)stream);
+  return speed_max_2d_t<double>(p, (const double*)u, nx, ny, speed2, &w, (hipStream_t)stream);
 }
 
 int32_t wzn_rk3_run_2d(const wzn_params* p, void* u, void* stage, int64_t nx, int64_t ny,
@@ -283,11 +363,12 @@ int32_t wzn_rk3_run_2d(const wzn_params* p, void* u, void* stage, int64_t nx, in
   if (nsteps < 0) return set_error(WZN_ERR_ARG, "nsteps < 0");
   if (!dt_in && !(cfl > 0.0)) return set_error(WZN_ERR_ARG, "cfl must be positive");
   Workspace w = make_workspace(ws);
-  if (p->dtype == WZN_FP32)
-    return rk3_run_2d_t<float>(p, (float*)u, (float*)stage, nx, ny, dx, dy, cfl, nsteps, dt_in,
-                               dt_out, &w, (hipStream_t)stream);
-  return rk3_run_2d_t<double>(p, (double*)u, (double*)stage, nx, ny, dx, dy, cfl, nsteps, dt_in,
-                              dt_out, &w, (hipStream_t)stream);
+  const bool f32 = p->dtype == WZN_FP32;
+  st = f32 ? rk3_run_2d_t<float>(p, (float*)u, (float*)stage, nx, ny, dx, dy, cfl, nsteps,
+                                 dt_in, dt_out, &w, (hipStream_t)stream)
+           : rk3_run_2d_t<double>(p, (double*)u, (double*)stage, nx, ny, dx, dy, cfl, nsteps,
+                                  dt_in, dt_out, &w, (hipStream_t)stream);
+  return scanned(st, p, u, 4 * nx * ny, f32, &w, stream);
 }
 
 int32_t wzn_rk3_step_2d(const wzn_params* p, void* u, void* stage, int64_t nx, int64_t ny,
@@ -318,8 +399,9 @@ int32_t wzn_batched_rk3_run_1d(const wzn_params* p, void* u, void* stage, int64_
     if (!ok) return set_error(WZN_ERR_ARG, "unsupported batched tuning (nt=%d, k=%d)", nt, k);
   }
   Workspace w = make_workspace(ws);
-  return batched_rk3_run_1d(p, (double*)u, (double*)stage, total, offsets, dx, order, batch,
-                            nsteps, cfl, tuning, dt_out, &w, (hipStream_t)stream);
+  return scanned(batched_rk3_run_1d(p, (double*)u, (double*)stage, total, offsets, dx, order,
+                                    batch, nsteps, cfl, tuning, dt_out, &w, (hipStream_t)stream),
+                 p, u, 3 * total, false, &w, stream);
 }
 
 int32_t wzn_rhs_1d_vjp(const wzn_params* p, const void* u, const void* mu, void* out, int64_t n,
@@ -331,8 +413,9 @@ int32_t wzn_rhs_1d_vjp(const wzn_params* p, const void* u, const void* mu, void*
   if (!u || !mu || !out) return set_error(WZN_ERR_ARG, "NULL array argument");
   if (out == u || out == mu) return set_error(WZN_ERR_ARG, "out must not alias u or mu");
   Workspace w = make_workspace(ws);
-  return rhs_1d_vjp(p, (const double*)u, (const double*)mu, (double*)out, n, dx, &w,
-                    (hipStream_t)stream);
+  return scanned(rhs_1d_vjp(p, (const double*)u, (const double*)mu, (double*)out, n, dx, &w,
+                            (hipStream_t)stream),
+                 p, out, 3 * n, false, &w, stream);
 }
 
 int32_t wzn_rk3_step_1d_vjp(const wzn_params* p, const void* stages, const void* lam_next,
@@ -347,8 +430,9 @@ int32_t wzn_rk3_step_1d_vjp(const wzn_params* p, const void* stages, const void*
   if (lam_prev == lam_next || lam_prev == stages || lam_prev == scratch)
     return set_error(WZN_ERR_ARG, "lam_prev must not alias the other arrays");
   Workspace w = make_workspace(ws);
-  return rk3_step_1d_vjp(p, (const double*)stages, (const double*)lam_next, (double*)lam_prev,
-                         (double*)scratch, n, dx, dt, alpha3, &w, (hipStream_t)stream);
+  return scanned(rk3_step_1d_vjp(p, (const double*)stages, (const double*)lam_next, (double*)lam_prev,
+                         (double*)scratch, n, dx, dt, alpha3, &w, (hipStream_t)stream),
+                 p, lam_prev, 3 * n, false, &w, stream);
 }
 
 int64_t wzn_rk3_adjoint_1d_work_doubles(int64_t n, int32_t ckpt_every) {
@@ -366,8 +450,9 @@ int32_t wzn_rk3_adjoint_1d(const wzn_params* p, const void* ckpts, int32_t nstep
   if (!ckpts || !dts || !alphas || !lam || !work) return set_error(WZN_ERR_ARG, "NULL argument");
   if (nsteps < 0 || ckpt_every < 1) return set_error(WZN_ERR_ARG, "bad nsteps / ckpt_every");
   Workspace w = make_workspace(ws);
-  return rk3_adjoint_1d(p, (const double*)ckpts, nsteps, ckpt_every, dts, alphas, (double*)lam,
-                        (double*)work, n, dx, &w, (hipStream_t)stream);
+  return scanned(rk3_adjoint_1d(p, (const double*)ckpts, nsteps, ckpt_every, dts, alphas, (double*)lam,
+                        (double*)work, n, dx, &w, (hipStream_t)stream),
+                 p, lam, 3 * n, false, &w, stream);
 }
 
 }  // extern "C"

@@ -55,6 +55,13 @@ template <typename T>
 int rhs_2d_t(const wzn_params* p, const T* u, T* dudt, int64_t nx, int64_t ny, double dx,
              double dy, Workspace* ws, hipStream_t s);
 template <typename T>
+int rhs_2d_strip_t(const wzn_params* p, const T* u, const T* ghost_lo, const T* ghost_hi,
+                   T* dudt, int64_t nx, int64_t ny, double dx, double dy, const double* alpha2,
+                   hipStream_t s);
+template <typename T>
+int speed_max_2d_t(const wzn_params* p, const T* u, int64_t nx, int64_t ny, double* out,
+                   Workspace* ws, hipStream_t s);
+template <typename T>
 int rk3_run_2d_t(const wzn_params* p, T* u, T* stage, int64_t nx, int64_t ny, double dx,
                  double dy, double cfl, int32_t nsteps, const double* dt_in, double* dt_out,
                  Workspace* ws, hipStream_t s);
@@ -83,6 +90,14 @@ int rk3_adjoint_1d(const wzn_params* p, const double* ckpts, int32_t nsteps, int
 int rhs_1d(const wzn_params* p, const double* u, double* dudt, int64_t n, double dx,
            Workspace* ws, hipStream_t s);
 int reconstruct(const wzn_params* p, const double* f, double* fhat, int64_t m, hipStream_t s);
+int rhs_1d_slab(const wzn_params* p, const double* u, const double* ghost_lo,
+                const double* ghost_hi, double* dudt, int64_t n, double dx, const double* alpha,
+                hipStream_t s);
+int speed_max_1d(const wzn_params* p, const double* u, int64_t n, double* out, Workspace* ws,
+                 hipStream_t s);
+// NaN / Inf scan of an output (the debug_nonfinite mode): synchronises s; WZN_ERR_NONFINITE
+// if any value of x[0 .. count) is not finite
+int debug_nonfinite_scan(const void* x, int64_t count, bool f32, Workspace* ws, hipStream_t s);
 int rk3_run_1d(const wzn_params* p, double* u, double* stage, int64_t n, double dx, double cfl,
                int32_t nsteps, const double* dt_in, const double* alpha_in, double* dt_out,
                double* alpha_out, Workspace* ws, hipStream_t s);

@@ -14,7 +14,8 @@ namespace wzn {
 
 // SPEED (a.speed_next set) is a template parameter rather than a branch: one kernel holding
 // both inlined tile variants is register-allocated for their union.
-template <int NT, int K, int SYS, typename T, bool SPLIT, bool SPEED, bool SW, int WT>
+template <int NT, int K, int SYS, typename T, bool SPLIT, bool SPEED, bool SW, int WT,
+          bool GHOST>
 __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T* W = reinterpret_cast<T*>(lds_raw);
@@ -42,7 +43,8 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
   const int64_t g0 = (int64_t)blockIdx.x * (NT * K);
   const int64_t rowoff = (int64_t)blockIdx.y * a.row_stride;
   double smax = 0.0;
-  row_tile<NT, K, SYS, T, SPEED, SPLIT, SW, WT>(a, g0, rowoff, T(alpha_d), dt, W, EX, smax);
+  row_tile<NT, K, SYS, T, SPEED, SPLIT, SW, WT, GHOST>(a, g0, rowoff, T(alpha_d), dt, W, EX,
+                                                       smax);
   if constexpr (SPEED) {
     const double m = block_max<NT>(smax, red);
     if (tid == 0) atomic_max_pos(a.speed_next, m);
@@ -53,21 +55,21 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
 
 // ------------------------------------------------------------------ host side
 template <int NT, int K, int SYS, typename T, bool SPLIT, bool SPEED, bool SW = false,
-          int WT = WEIGHTS_ZN>
+          int WT = WEIGHTS_ZN, bool GHOST = false>
 static int launch_row_ts(const RowArgs<T>& a, int64_t rows, hipStream_t s) {
   constexpr int TT = NT * K;
   const int64_t blocks = (a.n + TT - 1) / TT;
   const size_t lds = tile_lds_bytes<NT, K, SYS, T, SPLIT>();
   static bool attr_set = false;
   if (!attr_set) {
-    if (hipFuncSetAttribute((const void*)row_kernel<NT, K, SYS, T, SPLIT, SPEED, SW, WT>,
+    if (hipFuncSetAttribute((const void*)row_kernel<NT, K, SYS, T, SPLIT, SPEED, SW, WT, GHOST>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
       return set_error(WZN_ERR_HIP, "hipFuncSetAttribute(row_kernel) failed");
     attr_set = true;
   }
   if (blocks > 0x7fffffff || rows > 65535)
     return set_error(WZN_ERR_SIZE, "grid too large for the row kernel");
-  hipLaunchKernelGGL((row_kernel<NT, K, SYS, T, SPLIT, SPEED, SW, WT>),
+  hipLaunchKernelGGL((row_kernel<NT, K, SYS, T, SPLIT, SPEED, SW, WT, GHOST>),
                      dim3((unsigned)blocks, (unsigned)rows), dim3(NT), lds, s, a);
   return check_launch("row_kernel");
 }
@@ -87,6 +89,13 @@ static int launch_row_t(const RowArgs<T>& a, int64_t rows, hipStream_t s) {
 
 int launch_rows(const RowArgs<double>& a, int sys, int64_t rows, const Tuning1D& tn,
                 hipStream_t s) {
+  if (a.ghost_lo) {
+    // slab of a longer row: the 1D Euler right-hand side in one launch shape
+    if (sys != SYS_EULER1 || a.mode != MODE_RHS || a.weights != WEIGHTS_ZN)
+      return set_error(WZN_ERR_UNSUPPORTED, "ghost cells: 1D Euler right-hand side only");
+    return launch_row_ts<256, 4, SYS_EULER1, double, true, false, false, WEIGHTS_ZN, true>(a, rows,
+                                                                                           s);
+  }
   if (a.weights == WEIGHTS_Z) {
     // the WENO-Z comparison weights run in one launch shape per 1D system (the tuning
     // applies to the paper's weights)

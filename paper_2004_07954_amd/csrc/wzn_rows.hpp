@@ -24,6 +24,10 @@ struct RowArgs {
   int mode;
   int split;           // SPLIT_LF, or SPLIT_SW (2D x sweep only; alpha is then unused)
   int weights;         // WEIGHTS_ZN, or WEIGHTS_Z (1D fp64 only)
+  // slab of a longer 1D row (one GPU's share): its three cells below and above come from
+  // these [nvar][3] arrays instead of the boundary condition (1D Euler right-hand side only)
+  const T* ghost_lo;
+  const T* ghost_hi;
   double rk_a, rk_b;
   double adv, gamma, eps_s, A;
   double inv_gamma, inv_gm1;  // 1 / gamma, 1 / (gamma - 1) (Steger-Warming split)

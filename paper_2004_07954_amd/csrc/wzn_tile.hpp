@@ -234,8 +234,23 @@ constexpr int tile_ex_elems() { return (8 + NT / 64) * SysInfo<SYS>::NV; }
 // interface of the previous lane (cross-lane permute), of the previous wave (LDS) or, for the
 // tile's first cell, the boundary interface.  W: dynamic LDS of tile_lds_bytes(); EX: LDS of
 // tile_ex_elems() elements.  All threads of the workgroup must call it (it contains barriers).
+// Element (component c, in-row cell g in [-3, n + 2]) of the stage input: the boundary
+// condition's index map, or (GHOST) the caller's ghost cells of a slab of a longer row (cells
+// -3..-1 from ghost_lo, n..n+2 from ghost_hi, [nvar][3] each).  Cells past n + 2 only feed
+// interfaces of cells that are not stored.
+template <bool GHOST, typename T>
+__device__ __forceinline__ T row_elem(const RowArgs<T>& a, int c, int g, int n, int64_t rowoff) {
+  if constexpr (GHOST) {
+    if (g < 0) return a.ghost_lo[c * 3 + g + 3];
+    if (g >= n) return a.ghost_hi[c * 3 + min(g - n, 2)];
+    return a.uin[c * a.plane + rowoff + g];
+  } else {
+    return a.uin[c * a.plane + rowoff + bc_cell(g, n, a.bc)];
+  }
+}
+
 template <int NT, int K, int SYS, typename T, bool SPEED, bool SPLIT = false, bool SW = false,
-          int WT = WEIGHTS_ZN>
+          int WT = WEIGHTS_ZN, bool GHOST = false>
 __device__ __forceinline__ void row_tile(const RowArgs<T>& a, int64_t g0l, int64_t rowoff,
                                          T alpha, double dt, T* W, T* EX, double& smax) {
   static_assert(!SW || SYS == SYS_EULER2X, "the Steger-Warming split is for the 2D x sweep");
@@ -273,7 +288,7 @@ __device__ __forceinline__ void row_tile(const RowArgs<T>& a, int64_t g0l, int64
           load_run<K, T>(up + c0, u, ((uintptr_t)(up + g0) & 15) == 0);
         } else {
 #pragma unroll
-          for (int j = 0; j < K; ++j) u[j] = up[bc_cell(c0 + j, n, a.bc)];
+          for (int j = 0; j < K; ++j) u[j] = row_elem<GHOST, T>(a, c, c0 + j, n, rowoff);
         }
 #pragma unroll
         for (int j = 0; j < K; ++j) Ureg[j][c] = u[j];
@@ -304,10 +319,9 @@ __device__ __forceinline__ void row_tile(const RowArgs<T>& a, int64_t g0l, int64
       // ---- halo cells -3, -2, -1, T, T+1, T+2 on threads 0..5
       if (tid < 6) {
         const int p = tid < 3 ? tid : TT + tid;
-        const int cell = bc_cell(g0 + p - 3, n, a.bc);
         T U[NV], F[NV];
 #pragma unroll
-        for (int c = 0; c < NV; ++c) U[c] = a.uin[c * a.plane + rowoff + cell];
+        for (int c = 0; c < NV; ++c) U[c] = row_elem<GHOST, T>(a, c, g0 + p - 3, n, rowoff);
         const int q = tpos<NT, K>(p);
         if constexpr (SW) {
           T wp[NV], wm[NV];

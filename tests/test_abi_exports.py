@@ -42,6 +42,7 @@ def test_host_only_calls():
     assert p.abi_version == _lib.WZN_ABI_VERSION and p.A == 10.0 and p.eps == 1e-40
     assert p.p_C == 2 and p.q == 1 and p.gamma == 1.4
     assert L.wzn_status_string(0) == b"ok"
+    assert L.wzn_status_string(_lib.WZN_ERR_NONFINITE) == b"non-finite output"
     assert L.wzn_workspace_bytes(C.byref(p), 1 << 20, 1) >= 256
     # n < 6 is rejected before anything is enqueued
     rc = L.wzn_rhs_1d(C.byref(p), C.c_void_p(256), C.c_void_p(512), 5, 0.1, C.c_void_p(1024),
@@ -55,6 +56,11 @@ def test_host_only_calls():
     rc = L.wzn_rhs_1d(C.byref(p), C.c_void_p(256), C.c_void_p(512), 100, 0.1,
                       C.c_void_p(1000), None)
     assert rc == _lib.WZN_ERR_ARG  # unaligned workspace
+    p.debug_nonfinite = 2
+    rc = L.wzn_rhs_1d(C.byref(p), C.c_void_p(256), C.c_void_p(512), 100, 0.1,
+                      C.c_void_p(1024), None)
+    assert rc == _lib.WZN_ERR_ARG and b"debug_nonfinite" in L.wzn_last_error()
+    p.debug_nonfinite = 0
 
 
 def test_row_tuning_host_calls():
