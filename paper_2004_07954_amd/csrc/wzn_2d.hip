@@ -65,6 +65,14 @@ template <int NG, int K>
 struct ColTile {
   static constexpr int TY = NG * K;
   static constexpr int NPOS = TY + 6;
+  // the six halo positions (0..2 above the tile, TY+3..TY+5 below) are staged by the first
+  // HG groups, HPG each: one each when there are at least six groups, else two each
+  static constexpr int HPG = NG >= 6 ? 1 : 2;
+  static constexpr int HG = 6 / HPG;
+  static __device__ __forceinline__ int halo_pos(int g, int hh) {
+    if constexpr (NG >= 6) return g < 3 ? g : TY + g;
+    else return hh == 0 ? g : TY + 3 + g;
+  }
 };
 
 // y flux G = (rho v, rho u v, rho v^2 + p, v (E + p)) of a 2D Euler state, through one
@@ -111,19 +119,33 @@ __device__ __forceinline__ void col_state(const ColArgs<T>& a, int y, int ny, in
 // then w^- = w^+ - 2 alpha U in place).  The lower interface of a group's first row is the
 // last interface of the group below (LDS), of the previous iteration's last group (carried in
 // LDS), or at the segment's first row the boundary interface, reconstructed once per segment.
-// Four waves per SIMD (128 VGPRs; the fp64 variant with the wave-speed epilogue spills a few
-// bytes, which costs far less than dropping to three waves).
+// Two register budgets:
+//  - four waves per SIMD (128 VGPRs): the state of the next iteration is loaded after the
+//    finish, and Lx and U^n of all components are loaded together before the second phase's
+//    windows;
+//  - (PF, the fp64 Steger-Warming split, whose flux arithmetic needs more registers) three
+//    waves per SIMD (168 VGPRs): the next iteration's state is loaded before the finish, and
+//    each component's Lx and U^n one window ahead, so that their latency overlaps arithmetic.
+template <typename T, bool SW>
+struct ColPrefetch {
+  static constexpr bool value = SW && sizeof(T) == 8;
+};
 template <int NG, int K, typename T, bool SPEED, bool SW, bool GHOST>
-__global__ __launch_bounds__(64 * NG) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ __launch_bounds__(64 * NG)
+__attribute__((amdgpu_waves_per_eu(ColPrefetch<T, SW>::value ? 3 : 4)))
 void col_kernel(ColArgs<T> a) {
   static_assert(NG >= 4, "the segment's boundary interface uses one group per component");
+  constexpr bool PF = ColPrefetch<T, SW>::value;
   using CT = ColTile<NG, K>;
   constexpr int TY = CT::TY, NPOS = CT::NPOS;
   __shared__ T W[4 * NPOS * 64];
   __shared__ T XF[(NG - 1) * 4 * 64];
   __shared__ T CARRY[2][4 * 64];
   __shared__ double red[2][NG];
-  const int col = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int col = threadIdx.x & 63;
+  // the row group is the wave index: uniform across the wave, so held in a scalar register
+  // (the group branches below are then scalar branches, not exec masks)
+  const int g = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nx = (int)a.nx, ny = (int)a.ny;
   const int x = blockIdx.x * 64 + col;
   const bool xin = x < nx;
@@ -165,8 +187,46 @@ void col_kernel(ColArgs<T> a) {
   double sxm = 0.0, sym = 0.0;
 
   T Ureg[K][4];   // own rows: state, then (second phase) the base of the output
-  T HU[2][4];     // halo rows of groups 0..2 (top row g, bottom row TY + 3 + g)
+  T HU[CT::HPG][4];  // halo rows staged by this group (groups below CT::HG)
   T fh[4][K];
+  // the state of the group's own rows and halo rows of the iteration starting at row y0
+  auto load_rows = [&](int y0, T (&Ur)[K][4], T (&Hr)[CT::HPG][4]) {
+#pragma unroll
+    for (int j = 0; j < K; ++j) col_state<GHOST, T>(a, y0 + g * K + j, ny, nx, xc, Ur[j]);
+    if (g < CT::HG) {
+#pragma unroll
+      for (int hh = 0; hh < CT::HPG; ++hh)
+        col_state<GHOST, T>(a, y0 + CT::halo_pos(g, hh) - 3, ny, nx, xc, Hr[hh]);
+    }
+  };
+  // Lx and U^n of component c of the group's own rows (rows past the segment read the
+  // segment's first row instead: every load is in bounds, and those rows are never stored)
+  auto load_base = [&](int y0, int c, T (&lx)[K], T (&un)[K]) {
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      const int y = y0 + g * K + j;
+      const int64_t gi = (int64_t)(y < ye ? y : ys) * nx + xc;
+      lx[j] = a.lx[c * a.plane + gi];
+      un[j] = a.mode == MODE_STAGE && a.un ? a.un[c * a.plane + gi] : T(0);
+    }
+  };
+  // replace the state of component c by the base of the output: Lx (RHS) or
+  // fma(b_s dt, Lx, fma(a_s, U^n, b_s U)) (stage), so that the output is fma(cdt, Ly, base)
+  // with cdt = 1 or b_s dt
+  auto combine = [&](int c, const T (&lx)[K], const T (&un)[K]) {
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      T base = lx[j];
+      if (a.mode == MODE_STAGE) {
+        T b = T(a.rk_b) * Ureg[j][c];
+        if (a.un) b = fma_t(T(a.rk_a), un[j], b);
+        base = fma_t(cdt, lx[j], b);
+      }
+      Ureg[j][c] = base;
+      asm volatile("" : "+v"(Ureg[j][c]));  // combine here, not in the epilogue
+    }
+  };
+  if (ys < ye) load_rows(ys, Ureg, HU);
   int it = 0;
   for (int y0 = ys; y0 < ye; y0 += TY, ++it) {
     const int par = it & 1;
@@ -174,8 +234,6 @@ void col_kernel(ColArgs<T> a) {
     for (int ph = 0; ph < 2; ++ph) {
       __syncthreads();  // W, XF and CARRY of the previous phase / iteration are consumed
       if (ph == 0) {
-#pragma unroll
-        for (int j = 0; j < K; ++j) col_state<GHOST, T>(a, y0 + g * K + j, ny, nx, xc, Ureg[j]);
 #pragma unroll
         for (int j = 0; j < K; ++j) {
           T G[4];
@@ -190,11 +248,10 @@ void col_kernel(ColArgs<T> a) {
             for (int c = 0; c < 4; ++c) W[(c * NPOS + p) * 64 + col] = fma_t(alpha, Ureg[j][c], G[c]);
           }
         }
-        if (g < 3) {
+        if (g < CT::HG) {
 #pragma unroll
-          for (int hh = 0; hh < 2; ++hh) {
-            const int p = hh == 0 ? g : TY + 3 + g;
-            col_state<GHOST, T>(a, y0 + p - 3, ny, nx, xc, HU[hh]);
+          for (int hh = 0; hh < CT::HPG; ++hh) {
+            const int p = CT::halo_pos(g, hh);
             T G[4];
             if constexpr (SW) {
               // (the second phase re-reads the halo state rather than holding it)
@@ -227,10 +284,10 @@ void col_kernel(ColArgs<T> a) {
             }
           }
         }
-        if (g < 3) {
+        if (g < CT::HG) {
 #pragma unroll
-          for (int hh = 0; hh < 2; ++hh) {
-            const int p = hh == 0 ? g : TY + 3 + g;
+          for (int hh = 0; hh < CT::HPG; ++hh) {
+            const int p = CT::halo_pos(g, hh);
             if constexpr (SW) {
               T Uh[4], G[4];
               col_state<GHOST, T>(a, y0 + p - 3, ny, nx, xc, Uh);
@@ -246,39 +303,18 @@ void col_kernel(ColArgs<T> a) {
             }
           }
         }
-        // (Steger-Warming: keep the loads below from being hoisted into the split arithmetic
-        // above, where their registers would be live at the same time)
-        if constexpr (SW) asm volatile("" ::: "memory");
-        // the state is not needed past this point: replace it by the base of the output,
-        // Lx (RHS) or fma(b_s dt, Lx, fma(a_s, U^n, b_s U)) (stage), so that the output is
-        // fma(cdt, Ly, base) with cdt = 1 or b_s dt
-        // all loads of the row group are issued before any is combined (the register pins
-        // would otherwise wait for each load before issuing the next)
-        T lxv[K][4], unv[K][4];
+        if constexpr (!PF) {
+          // (Steger-Warming: keep the loads below from being hoisted into the split arithmetic
+          // above, where their registers would be live at the same time)
+          if constexpr (SW) asm volatile("" ::: "memory");
+          // the state is not needed past this point: all loads of the row group are issued
+          // before any is combined (the register pins would otherwise wait for each load
+          // before issuing the next)
+          T lxv[4][K], unv[4][K];
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
-          const int y = y0 + g * K + j;
-          const bool ok = y < ye && xin;
-          const int64_t gi = (int64_t)(ok ? y : ys) * nx + xc;
+          for (int c = 0; c < 4; ++c) load_base(y0, c, lxv[c], unv[c]);
 #pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            lxv[j][c] = ok ? a.lx[c * a.plane + gi] : T(0);
-            unv[j][c] = a.mode == MODE_STAGE && a.un && ok ? a.un[c * a.plane + gi] : T(0);
-          }
-        }
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-#pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            T base = lxv[j][c];
-            if (a.mode == MODE_STAGE) {
-              T b = T(a.rk_b) * Ureg[j][c];
-              if (a.un) b = fma_t(T(a.rk_a), unv[j][c], b);
-              base = fma_t(cdt, lxv[j][c], b);
-            }
-            Ureg[j][c] = base;
-            asm volatile("" : "+v"(Ureg[j][c]));  // combine here, not in the epilogue
-          }
+          for (int c = 0; c < 4; ++c) combine(c, lxv[c], unv[c]);
         }
       }
       __syncthreads();
@@ -294,10 +330,15 @@ void col_kernel(ColArgs<T> a) {
         else CARRY[1][g * 64 + col] += h[0];
       }
 
-      // windows: thread (col, g) owns the upper interfaces of rows gK .. gK+K-1
+      // windows: thread (col, g) owns the upper interfaces of rows gK .. gK+K-1.  (PF: in
+      // the second phase each component's state is replaced by the base after its window,
+      // with the loads of its Lx and U^n issued one window ahead.)
+      T lxq[2][K], unq[2][K];
+      if (PF && ph == 1) load_base(y0, 0, lxq[0], unq[0]);
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         T v[K + 4], h[K];
+        if (PF && ph == 1 && c < 3) load_base(y0, c + 1, lxq[(c + 1) & 1], unq[(c + 1) & 1]);
         if (ph == 0) {
 #pragma unroll
           for (int i = 0; i < K + 4; ++i) v[i] = W[(c * NPOS + g * K + 1 + i) * 64 + col];
@@ -316,9 +357,15 @@ void col_kernel(ColArgs<T> a) {
             fh[c][m] += h[K - 1 - m];
             asm volatile("" : "+v"(fh[c][m]));
           }
+          if constexpr (PF) combine(c, lxq[c & 1], unq[c & 1]);
         }
       }
     }
+    // (PF) the next iteration's rows are loaded now: the loads are in flight during the
+    // exchange and the finish below
+    T Unx[K][4], HUnx[CT::HPG][4];
+    const bool more = y0 + TY < ye;
+    if (PF && more) load_rows(y0 + TY, Unx, HUnx);
     // ---- exchange the groups' last interfaces
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
@@ -353,6 +400,18 @@ void col_kernel(ColArgs<T> a) {
         }
       }
     }
+    if (!PF && more) {
+      load_rows(y0 + TY, Ureg, HU);
+    } else if (more) {
+#pragma unroll
+      for (int j = 0; j < K; ++j)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) Ureg[j][c] = Unx[j][c];
+#pragma unroll
+      for (int hh = 0; hh < CT::HPG; ++hh)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) HU[hh][c] = HUnx[hh][c];
+    }
   }
   if constexpr (SPEED) {
     sxm = wave_max(sxm);
@@ -379,8 +438,13 @@ template <int NG, int K, typename T>
 static int launch_col_t(ColArgs<T> a, hipStream_t s) {
   constexpr int TY = ColTile<NG, K>::TY;
   const int64_t bx = (a.nx + 63) / 64;
-  // about four workgroups per CU: split the rows into segments (multiples of TY rows)
-  int64_t nseg = (1024 + bx - 1) / bx;
+  // Split the rows into segments (multiples of TY rows) for several rounds of resident
+  // workgroups: four rounds at four waves per SIMD, eight at three (PF).  With a single round
+  // the workgroups dispatched last get the smallest share of the SIMDs and finish last, so the
+  // CUs drain from four resident waves per SIMD to one (measured: one round is 3-5 % slower).
+  const bool pf = a.split == SPLIT_SW ? ColPrefetch<T, true>::value : ColPrefetch<T, false>::value;
+  const int64_t target = pf ? 256 * 3 * 8 : 256 * 4 * 4;
+  int64_t nseg = (target + bx - 1) / bx;
   const int64_t maxseg = (a.ny + TY - 1) / TY;
   if (nseg > maxseg) nseg = maxseg;
   if (nseg < 1) nseg = 1;
