@@ -280,6 +280,14 @@ __device__ __forceinline__ void row_tile(const RowArgs<T>& a, int64_t g0l, int64
     if (ph == 0) {
       // ---- own cells: load, flux, split.  w^+ = F + alpha U, w^- = w^+ - 2 alpha U in every
       //      layout, so that the split layout forms w^- from the staged w^+ with the same bits.
+      //      The halo cells -3, -2, -1, T, T+1, T+2 of threads 0..5 are loaded first, so that
+      //      their loads are in flight together with the own cells'.
+      T Uh[NV];
+      const int hp = tid < 3 ? tid : TT + tid;
+      if (tid < 6) {
+#pragma unroll
+        for (int c = 0; c < NV; ++c) Uh[c] = row_elem<GHOST, T>(a, c, g0 + hp - 3, n, rowoff);
+      }
 #pragma unroll
       for (int c = 0; c < NV; ++c) {
         const T* up = a.uin + c * a.plane + rowoff;
@@ -316,12 +324,12 @@ __device__ __forceinline__ void row_tile(const RowArgs<T>& a, int64_t g0l, int64
           }
         }
       }
-      // ---- halo cells -3, -2, -1, T, T+1, T+2 on threads 0..5
+      // ---- halo cells on threads 0..5
       if (tid < 6) {
-        const int p = tid < 3 ? tid : TT + tid;
+        const int p = hp;
         T U[NV], F[NV];
 #pragma unroll
-        for (int c = 0; c < NV; ++c) U[c] = row_elem<GHOST, T>(a, c, g0 + p - 3, n, rowoff);
+        for (int c = 0; c < NV; ++c) U[c] = Uh[c];
         const int q = tpos<NT, K>(p);
         if constexpr (SW) {
           T wp[NV], wm[NV];
