@@ -1,0 +1,93 @@
+"""Runs captured in a HIP graph (torch.cuda.CUDAGraph), as the benchmark launches them: every
+replay, with the program's own eager work and synchronisations between the replays, equals
+the eager run bit for bit.  The library clears its reduction slots and queue counter with a
+kernel, never with a memset node."""
+import numpy as np
+import pytest
+
+from paper_2004_07954_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+REPLAYS = 3
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2004_07954_amd import api
+    return api
+
+
+def note(*args):
+    print("[gpu-case]", *args, flush=True)
+
+
+def _replays_match(run, u, u0, ref, side):
+    """Capture run(u) once, then replay it REPLAYS times from u0; every replay must equal
+    `ref`.  `side` is eager work run between the replays."""
+    import torch
+    g = torch.cuda.CUDAGraph()
+    u.copy_(u0)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        run(u)
+    for r in range(REPLAYS):
+        u.copy_(u0)
+        side()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(u, ref), "replay %d differs from the eager run" % r
+    del g
+
+
+def test_graph_rk3_run_1d(api):
+    import torch
+    note("graph: rk3_run_1d, n = 4099, 20 steps")
+    u0, dx = I.shu_osher_like(4099)
+    u0 = torch.tensor(u0, dtype=torch.float64, device="cuda")
+    stage = torch.empty((2,) + tuple(u0.shape), dtype=torch.float64, device="cuda")
+    u = u0.clone()
+    api.rk3_run_1d(u, dx, 20, cfl=0.5, stage=stage)
+    ref = u.clone()
+    other = torch.tensor(I.random_smooth_1d(1000, seed=3), dtype=torch.float64, device="cuda")
+    _replays_match(lambda t: api.rk3_run_1d(t, dx, 20, cfl=0.5, stage=stage), u, u0, ref,
+                   lambda: api.rhs_1d(other, 0.01))
+
+
+def test_graph_rk3_run_2d(api):
+    import torch
+    for split in ("lf", "sw"):
+        note("graph: rk3_run_2d, 200 x 130, 5 steps,", split)
+        u0, dx, dy = I.riemann_2d(2, 200)
+        u0 = torch.tensor(u0[:, :130, :], dtype=torch.float64, device="cuda").contiguous()
+        prm = api.params("euler", split=split)
+        stage = torch.empty((2,) + tuple(u0.shape), dtype=torch.float64, device="cuda")
+        u = u0.clone()
+        api.rk3_run_2d(u, dx, dy, 5, prm=prm, stage=stage)
+        ref = u.clone()
+        other = torch.tensor(I.random_smooth_1d(500, seed=4), dtype=torch.float64,
+                             device="cuda")
+        _replays_match(lambda t: api.rk3_run_2d(t, dx, dy, 5, prm=prm, stage=stage), u, u0,
+                       ref, lambda: api.rk3_run_1d(other, 0.01, 1))
+
+
+def test_graph_batched(api):
+    import torch
+    note("graph: batched_rk3_run_1d, 96 instances, 10 steps")
+    U, offs, dx = I.shock_tube_batch(96, seed=12, nmin=256, nmax=3000)
+    U0 = torch.tensor(U, dtype=torch.float64, device="cuda")
+    offg = torch.tensor(offs, dtype=torch.int64, device="cuda")
+    dxg = torch.tensor(dx, dtype=torch.float64, device="cuda")
+    order = api.lpt_order(np.diff(offs))
+    stage = torch.empty((2, 3, U.shape[1]), dtype=torch.float64, device="cuda")
+    for tn in (api.batch_tuning(128, 2, 0, 0), api.batch_tuning(256, 2, 0, 1)):
+        u = U0.clone()
+        api.batched_rk3_run_1d(u, offg, dxg, 10, order=order, tuning=tn, stage=stage)
+        ref = u.clone()
+        assert torch.isfinite(ref).all()
+        _replays_match(lambda t: api.batched_rk3_run_1d(t, offg, dxg, 10, order=order,
+                                                        tuning=tn, stage=stage),
+                       u, U0, ref, lambda: torch.cuda.synchronize())
