@@ -342,9 +342,34 @@ def bench_adjoint(n=65536, nsteps=400, ckpt=20, reps=3):
         bw.append(t2 - t1)
     fw, bw = float(np.median(fw[1:])), float(np.median(bw[1:]))
     assert torch.isfinite(lam0).all().item()
+    # the same passes captured once in HIP graphs and replayed: GPU time without the host's
+    # per-kernel launch cost (a stage kernel at this N runs about as long as its launch takes)
+    cap = adjoint.CapturedAdjoint(U0, dx, nsteps, 0.5, prm, ckpt)
+    fg, bg = [], []
+    for _ in range(reps + 1):
+        s0, s1, s2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        torch.cuda.synchronize()
+        s0.record()
+        UTg = cap.forward(U0)
+        s1.record()
+        lamTg = torch.zeros_like(UTg)
+        lamTg[0] = UTg[0] - rho_t
+        torch.cuda.synchronize()
+        s1b = torch.cuda.Event(enable_timing=True)
+        s1b.record()
+        lamg = cap.backward(lamTg)
+        s2.record()
+        torch.cuda.synchronize()
+        fg.append(s0.elapsed_time(s1))
+        bg.append(s1b.elapsed_time(s2))
+    fg, bg = float(np.median(fg[1:])), float(np.median(bg[1:]))
     return {"workload": "adjoint_euler1d_periodic_n%d_%dsteps_ckpt%d" % (n, nsteps, ckpt),
             "forward_ms": fw * 1e3, "backward_ms": bw * 1e3, "adjoint_fwd_ratio": bw / fw,
-            "timing": "host wall clock around synchronised GPU work, median of %d" % reps}
+            "timing": "host wall clock around synchronised GPU work, median of %d" % reps,
+            "forward_ms_graph": fg, "backward_ms_graph": bg, "adjoint_fwd_ratio_graph": bg / fg,
+            "graph_equals_eager": bool(torch.equal(lamg, lam0)),
+            "timing_graph": "HIP events around replays of the captured passes, median of %d"
+                            % reps}
 
 
 def main():

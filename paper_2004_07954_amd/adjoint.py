@@ -61,6 +61,49 @@ def backward_checkpointed(lamT, dx, dts, als, ckpts, ckpt_every=20, prm=None, wo
     return lam
 
 
+class CapturedAdjoint:
+    """The checkpointed forward run and the adjoint pass of one problem shape, each captured
+    once in a HIP graph and replayed per evaluation, so that a gradient costs the GPU work
+    only, not one host launch per kernel (at N = 65536 a stage kernel runs for about as long
+    as its launch takes).  Inputs are copied into the captured buffers:
+
+        cap = CapturedAdjoint(U0, dx, nsteps)
+        UT = cap.forward(U0_new)      # U_T; cap.dts, cap.als hold the recorded schedule
+        lam0 = cap.backward(lamT)     # dJ/dU_0 for dJ/dU_T = lamT, with that schedule
+
+    The returned tensors are the graphs' own buffers and are overwritten by the next replay.
+    """
+
+    def __init__(self, U0, dx, nsteps, cfl=0.5, prm=None, ckpt_every=20):
+        prm = prm or api.params("euler", bc="periodic")
+        self.U0 = U0.detach().clone().contiguous()
+        self.lamT = torch.zeros_like(self.U0)
+        # an eager pass first: it allocates the library workspace outside the graphs
+        UT, dts, als, ckpts = forward_checkpointed(self.U0, dx, nsteps, cfl, prm, ckpt_every)
+        backward_checkpointed(self.lamT, dx, dts, als, ckpts, ckpt_every, prm)
+        torch.cuda.synchronize()
+        self.g_fwd = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.g_fwd):
+            self.UT, self.dts, self.als, ck = forward_checkpointed(self.U0, dx, nsteps, cfl,
+                                                                   prm, ckpt_every)
+            self.ckpts = torch.stack(ck)
+        self.g_bwd = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.g_bwd):
+            self.lam0 = backward_checkpointed(self.lamT, dx, self.dts, self.als, self.ckpts,
+                                              ckpt_every, prm)
+
+    def forward(self, U0=None):
+        if U0 is not None:
+            self.U0.copy_(U0)
+        self.g_fwd.replay()
+        return self.UT
+
+    def backward(self, lamT):
+        self.lamT.copy_(lamT)
+        self.g_bwd.replay()
+        return self.lam0
+
+
 class WenoZNRK3(torch.autograd.Function):
     """U_T = RK3^nsteps(U_0) with WENO-ZN right-hand sides; backward = discrete adjoint with
     checkpointed recomputation (dt and alphas frozen at the forward's values)."""

@@ -91,3 +91,27 @@ def test_graph_batched(api):
         _replays_match(lambda t: api.batched_rk3_run_1d(t, offg, dxg, 10, order=order,
                                                         tuning=tn, stage=stage),
                        u, U0, ref, lambda: torch.cuda.synchronize())
+
+
+def test_graph_adjoint(api):
+    """The captured checkpointed forward and adjoint pass equal the eager ones bit for bit, on
+    replays with new initial states and new cotangents."""
+    import torch
+    from paper_2004_07954_amd import adjoint
+    note("graph: checkpointed forward + adjoint, n = 4096, 40 steps, checkpoints every 10")
+    n, nsteps, ck = 4096, 40, 10
+    u0, _, dx = I.adjoint_case(n=n, seed=5)
+    U0 = torch.tensor(u0, dtype=torch.float64, device="cuda")
+    prm = api.params("euler", bc="periodic")
+    cap = adjoint.CapturedAdjoint(U0, dx, nsteps, 0.5, prm, ck)
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    for r in range(REPLAYS):
+        Ur = U0 * (1.0 + 0.01 * r)
+        lamT = torch.randn(U0.shape, generator=gen, dtype=torch.float64, device="cuda")
+        UT, dts, als, ckpts = adjoint.forward_checkpointed(Ur, dx, nsteps, 0.5, prm, ck)
+        lam0 = adjoint.backward_checkpointed(lamT, dx, dts, als, ckpts, ck, prm)
+        torch.cuda.synchronize()
+        assert torch.equal(cap.forward(Ur), UT), r
+        assert torch.equal(cap.dts, dts) and torch.equal(cap.als, als), r
+        assert torch.equal(cap.backward(lamT), lam0), r
+        torch.cuda.synchronize()
