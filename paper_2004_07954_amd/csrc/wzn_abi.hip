@@ -40,11 +40,14 @@ Tuning1D row_override() { return g_row_override; }
 
 // Launch shape of the 1D row kernel: the caller's override if set; otherwise, as measured on
 // MI355X, 1024-cell tiles with the signs staged one at a time from 3 * 2^18 cells (one round
-// of four workgroups per CU at 2^20 cells), 512-cell tiles from 2^15, else 256-cell tiles.
+// of four workgroups per CU at 2^20 cells), 512-cell tiles staged one sign at a time from 2^17
+// (5 % faster than both signs at once at 2^18, equal at 2^16), 512-cell tiles with both signs
+// from 2^15, else 256-cell tiles.
 Tuning1D tuning_1d(int nv, int64_t n) {
   if (nv == 1) return Tuning1D{64, 4, ROW_LDS_TILE};
   if (g_row_override.nt > 0) return g_row_override;
   if (n >= (int64_t)3 << 18) return Tuning1D{256, 4, ROW_LDS_SPLIT};
+  if (n >= (int64_t)1 << 17) return Tuning1D{256, 2, ROW_LDS_SPLIT};
   if (n >= (int64_t)1 << 15) return Tuning1D{256, 2, ROW_LDS_TILE};
   return Tuning1D{256, 1, ROW_LDS_TILE};
 }

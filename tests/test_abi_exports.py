@@ -73,6 +73,7 @@ def test_row_tuning_host_calls():
         autotune.set_row_tuning(0, 0)
         assert autotune.get_row_tuning(3, 1 << 20) == (256, 4, 1)
         assert autotune.get_row_tuning(3, 65536) == (256, 2, 0)
+        assert autotune.get_row_tuning(3, 1 << 18) == (256, 2, 1)
         assert autotune.get_row_tuning(3, 1000) == (256, 1, 0)
         assert autotune.get_row_tuning(1, 200) == (64, 4, 0)
         for shape in autotune.ROW_SHAPES:
