@@ -80,7 +80,7 @@ def cpu_baseline(n, budget_s=12.0):
     t0 = time.perf_counter()
     u1, _, _ = orc.rk3_run_1d(u, dx, 1, cfl=0.5)
     t1 = time.perf_counter() - t0
-    steps = max(1, min(40, int(budget_s / max(t1, 1e-3))))
+    steps = max(1, min(400, int(budget_s / max(t1, 1e-3))))
     t0 = time.perf_counter()
     orc.rk3_run_1d(u1, dx, steps, cfl=0.5)
     el = time.perf_counter() - t0
