@@ -417,9 +417,9 @@ def main():
 
     # launch shape of the stage kernel, chosen by timing the candidates before the timed run
     from paper_2004_07954_amd import autotune
-    tune_best, tune_ms = autotune.tune_rows(n, steps=30, shapes=[(256, 4, 1), (128, 4, 1),
-                                                                 (256, 2, 1), (256, 2, 0)],
-                                            log=log, apply=True)
+    tune_best, tune_ms = autotune.tune_rows(n, steps=100, shapes=[(256, 4, 1), (128, 4, 1),
+                                                                  (256, 2, 1), (256, 2, 0)],
+                                            log=log, apply=True, rounds=3)
     log("warmup", W, "steps, N =", n)
     if W:
         api.rk3_run_1d(u, dx, W, cfl=0.5, prm=prm, stage=stage)

@@ -99,10 +99,12 @@ def set_row_tuning(nt, k, layout=0):
     check(lib().wzn_set_row_tuning(int(nt), int(k), int(layout)))
 
 
-def tune_rows(n, steps=50, shapes=ROW_SHAPES, log=None, apply=True):
+def tune_rows(n, steps=50, shapes=ROW_SHAPES, log=None, apply=True, rounds=1):
     """Time the 1D Euler TVD-RK3 stage kernel at grid size n for every launch shape on
-    Shu-Osher-like data and (optionally) install the fastest process-wide.  Returns
-    ((nt, k, layout), {shape: ms per step})."""
+    Shu-Osher-like data and (optionally) install the fastest process-wide.  With rounds > 1
+    the shapes are timed in turn that many times and each keeps its best time, so that a
+    clock ramp or a noisy sample does not decide between shapes a few per cent apart.
+    Returns ((nt, k, layout), {shape: ms per step})."""
     from . import inputs as I
     u0, dx = I.shu_osher_like(n)
     base = torch.tensor(u0, dtype=torch.float64, device="cuda")
@@ -110,21 +112,24 @@ def tune_rows(n, steps=50, shapes=ROW_SHAPES, log=None, apply=True):
     stage = torch.empty((2,) + tuple(u.shape), dtype=torch.float64, device="cuda")
     prm = api.params("euler")
     timings = {}
-    for nt, k, lay in shapes:
-        set_row_tuning(nt, k, lay)
-        u.copy_(base)
-        api.rk3_run_1d(u, dx, 2, prm=prm, stage=stage)
-        u.copy_(base)
-        torch.cuda.synchronize()
-        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        s.record()
-        api.rk3_run_1d(u, dx, steps, prm=prm, stage=stage)
-        e.record()
-        torch.cuda.synchronize()
-        key = "%d/%d/%d" % (nt, k, lay)
-        timings[key] = s.elapsed_time(e) / steps
-        if log:
-            log("rows n=%d nt=%d k=%d layout=%d: %.4f ms/step" % (n, nt, k, lay, timings[key]))
+    for _ in range(max(1, rounds)):
+        for nt, k, lay in shapes:
+            set_row_tuning(nt, k, lay)
+            u.copy_(base)
+            api.rk3_run_1d(u, dx, 2, prm=prm, stage=stage)
+            u.copy_(base)
+            torch.cuda.synchronize()
+            s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            s.record()
+            api.rk3_run_1d(u, dx, steps, prm=prm, stage=stage)
+            e.record()
+            torch.cuda.synchronize()
+            key = "%d/%d/%d" % (nt, k, lay)
+            t = s.elapsed_time(e) / steps
+            timings[key] = min(t, timings.get(key, t))
+    if log:
+        for key, t in timings.items():
+            log("rows n=%d shape %s: %.4f ms/step" % (n, key, t))
     best = min(timings, key=timings.get)
     nt, k, lay = (int(x) for x in best.split("/"))
     set_row_tuning(nt, k, lay) if apply else set_row_tuning(0, 0)
