@@ -33,6 +33,8 @@ ROW_KERNEL_SOURCES = ("wzn_rows.hip", "wzn_rows.hpp", "wzn_tile.hpp", "wzn_devic
                       "wzn_1d.hip", "wzn_host.hpp")
 CHAR_KERNEL_SOURCES = ("wzn_char.hip", "wzn_rows.hpp", "wzn_tile.hpp", "wzn_device.hpp",
                        "wzn_host.hpp")
+EULER2D_KERNEL_SOURCES = ("wzn_2d.hip", "wzn_rows.hip", "wzn_rows.hpp", "wzn_tile.hpp",
+                          "wzn_device.hpp", "wzn_host.hpp")
 
 
 def kernel_source_hash(files):
@@ -126,10 +128,28 @@ def bench_2d(steps, dtype_name, warmup=3, split="lf"):
     bytes_stage = nx * ny * 4 * esz * (2 + 3 + 3) / 3.0
     stage_ms = ms / (3 * steps)
     gbs = bytes_stage / (stage_ms * 1e-3) / 1e9
-    return {"workload": wl, "dtype": dtype_name,
-            "steps": steps, "ms_per_step": ms / steps,
-            "value": nx * ny * 3 * steps / (ms * 1e-3), "unit": "cell-RHS/s",
-            "stage_ms": stage_ms, "hbm_gbs_algorithmic": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}
+    rec = {"workload": wl, "dtype": dtype_name,
+           "steps": steps, "ms_per_step": ms / steps,
+           "value": nx * ny * 3 * steps / (ms * 1e-3), "unit": "cell-RHS/s",
+           "stage_ms": stage_ms, "hbm_gbs_algorithmic": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}
+    if dtype_name == "f64":
+        # fp64 VALU side: the x sweep plus the column kernel per stage, from the committed
+        # counter profile of the 2D kernels (Steger-Warming steps run the column kernel with
+        # the wave-speed epilogue in their last stage only)
+        v = committed_profile("counters", "euler2d", "kernels", "valu_per_cell",
+                              EULER2D_KERNEL_SOURCES)
+        per_cell = None
+        if v and split == "lf":
+            per_cell = v.get("x_lf_f64", 0) + v.get("col_lf_f64_speed", 0)
+        elif v:
+            per_cell = v.get("x_sw_f64", 0) + (2 * v.get("col_sw_f64", 0) +
+                                               v.get("col_sw_f64_speed", 0)) / 3.0
+        ach = per_cell * nx * ny / (stage_ms * 1e-3) if per_cell else None
+        rec["roofline_alu"] = {"bound": "alu", "unit": "VALU lane-instr/s",
+                               "valu_instr_per_cell_stage": per_cell, "achieved": ach,
+                               "peak": VALU_LANE_PEAK,
+                               "frac": ach / VALU_LANE_PEAK if ach else None}
+    return rec
 
 
 def bench_batched(steps, baseline_sample=48, use_graph=True):
