@@ -73,6 +73,11 @@ def lib():
                                             C.POINTER(OrcParams), d, p]
         L.orc_rk3_run_1d_char_f64.argtypes = [i32, i64, p, d, d, C.c_int32,
                                               C.POINTER(OrcParams), d, p, p]
+        L.orc_rhs_2d_char_f64.argtypes = [i32, i32, i64, i64, p, p, d, d, p,
+                                          C.POINTER(OrcParams), d, p]
+        L.orc_roe_eigen_2d_f64.argtypes = [p, p, i32, d, p, p]
+        L.orc_rk3_run_2d_char_f64.argtypes = [i32, i32, i64, i64, p, d, d, d, C.c_int32, p,
+                                              C.POINTER(OrcParams), d, p]
         L.orc_num_threads.restype = C.c_int
         _LIB = L
     return _LIB
@@ -275,3 +280,42 @@ def rk3_run_1d_char(u, dx, nsteps, cfl=0.5, bc=BC_TRANSMISSIVE, prm=None, gamma=
 
 def num_threads():
     return int(lib().orc_num_threads())
+
+
+def rhs_2d_char(u, dx, dy, bcx=BC_TRANSMISSIVE, bcy=None, alpha8=None, prm=None, gamma=GAMMA):
+    """L(U) of 2D Euler [4, ny, nx] with each sweep's reconstruction in local characteristic
+    fields; returns (L, alpha8_used): the per-field alphas of the x sweep, then the y sweep."""
+    prm = prm or params()
+    bcy = bcx if bcy is None else bcy
+    u = _f64(u)
+    ny, nx = u.shape[-2], u.shape[-1]
+    out = np.zeros_like(u)
+    a_in = None if alpha8 is None else _f64(alpha8)
+    a_out = np.zeros(8)
+    lib().orc_rhs_2d_char_f64(bcx, bcy, nx, ny, _ptr(u), _ptr(out), dx, dy, _ptr(a_in),
+                              C.byref(prm), gamma, _ptr(a_out))
+    return out, a_out
+
+
+def roe_eigen_2d(UL, UR, direction, gamma=GAMMA):
+    """(R, Lc) of the 2D flux Jacobian along x (direction 0) or y (1) at the Roe average of
+    two states (4x4 arrays)."""
+    R, Lc = np.zeros(16), np.zeros(16)
+    lib().orc_roe_eigen_2d_f64(_ptr(_f64(UL)), _ptr(_f64(UR)), int(direction), gamma, _ptr(R),
+                               _ptr(Lc))
+    return R.reshape(4, 4), Lc.reshape(4, 4)
+
+
+def rk3_run_2d_char(u, dx, dy, nsteps, cfl=0.5, bcx=BC_TRANSMISSIVE, bcy=None, dt=None,
+                    prm=None, gamma=GAMMA):
+    """nsteps TVD-RK3 steps of the 2D characteristic scheme; returns (u, dt[nsteps])."""
+    prm = prm or params()
+    bcy = bcx if bcy is None else bcy
+    u = _f64(u).copy()
+    ny, nx = u.shape[-2], u.shape[-1]
+    if dt is not None:
+        dt = _f64(np.broadcast_to(np.asarray(dt, dtype=np.float64), (nsteps,)))
+    dt_out = np.zeros(nsteps)
+    lib().orc_rk3_run_2d_char_f64(bcx, bcy, nx, ny, _ptr(u), dx, dy, cfl, nsteps, _ptr(dt),
+                                  C.byref(prm), gamma, _ptr(dt_out))
+    return u, dt_out

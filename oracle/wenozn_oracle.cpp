@@ -472,6 +472,149 @@ static void lf_alpha_2d(int64_t N, const double* u, const Phys& ph, double* ax, 
   *ay = my;
 }
 
+// ---------------------------------------------------------------- 2D Euler, local characteristic fields
+// The 1D procedure of Sec. 4.3 applied along each sweep direction n = (nx, ny) of the
+// dimension-by-dimension scheme (eq:2d): (1, 0) for the x sweep, (0, 1) for the y sweep.  At
+// x_{i+1/2} (or y_{j+1/2}) the flux Jacobian A_n = nx dF/dU + ny dG/dU is taken at the Roe
+// average of the two neighbouring states (u, v and H = (E + p)/rho weighted by sqrt(rho),
+// c^2 = (gamma - 1)(H - (u^2 + v^2)/2)), with u_n = u nx + v ny, u_t = -u ny + v nx.  Its
+// eigenvalues are u_n - c, u_n, u_n, u_n + c; R has the right eigenvectors as columns,
+//   (1, u - c nx, v - c ny, H - c u_n), (1, u, v, q^2/2), (0, -ny, nx, u_t),
+//   (1, u + c nx, v + c ny, H + c u_n),
+// and Lc = R^{-1}.  The split, the per-field alphas (max over interior cells of |lambda_k| of
+// the cell states, per sweep and per RHS evaluation) and ghat = WZN(g+) + WZN(g-) mirrored
+// follow the 1D procedure; the interface flux is R ghat.
+template <class T>
+static void roe_eigen_2d(const T* UL, const T* UR, int dir, const Phys& ph, T R[4][4],
+                         T Lc[4][4]) {
+  const T g = T(ph.gamma);
+  const T nx = dir == 0 ? T(1) : T(0), ny = dir == 0 ? T(0) : T(1);
+  const T uL = UL[1] / UL[0], vL = UL[2] / UL[0];
+  const T uR = UR[1] / UR[0], vR = UR[2] / UR[0];
+  const T pL = (g - T(1)) * (UL[3] - T(1) / T(2) * UL[0] * (uL * uL + vL * vL));
+  const T pR = (g - T(1)) * (UR[3] - T(1) / T(2) * UR[0] * (uR * uR + vR * vR));
+  const T HL = (UL[3] + pL) / UL[0], HR = (UR[3] + pR) / UR[0];
+  const T sL = sqrtv(UL[0]), sR = sqrtv(UR[0]);
+  const T u = (sL * uL + sR * uR) / (sL + sR);
+  const T v = (sL * vL + sR * vR) / (sL + sR);
+  const T H = (sL * HL + sR * HR) / (sL + sR);
+  const T q2 = u * u + v * v;
+  const T c = sqrtv((g - T(1)) * (H - T(1) / T(2) * q2));
+  const T un = u * nx + v * ny, ut = -u * ny + v * nx;
+  const T col[4][4] = {{T(1), u - c * nx, v - c * ny, H - c * un},
+                       {T(1), u, v, T(1) / T(2) * q2},
+                       {T(0), -ny, nx, ut},
+                       {T(1), u + c * nx, v + c * ny, H + c * un}};
+  for (int r = 0; r < 4; ++r)
+    for (int f = 0; f < 4; ++f) R[r][f] = col[f][r];
+  const T b1 = (g - T(1)) / (c * c);
+  const T b2 = T(1) / T(2) * q2 * b1;
+  Lc[0][0] = T(1) / T(2) * (b2 + un / c);
+  Lc[0][1] = -T(1) / T(2) * (b1 * u + nx / c);
+  Lc[0][2] = -T(1) / T(2) * (b1 * v + ny / c);
+  Lc[0][3] = T(1) / T(2) * b1;
+  Lc[1][0] = T(1) - b2;
+  Lc[1][1] = b1 * u;
+  Lc[1][2] = b1 * v;
+  Lc[1][3] = -b1;
+  Lc[2][0] = -ut;
+  Lc[2][1] = -ny;
+  Lc[2][2] = nx;
+  Lc[2][3] = T(0);
+  Lc[3][0] = T(1) / T(2) * (b2 - un / c);
+  Lc[3][1] = -T(1) / T(2) * (b1 * u - nx / c);
+  Lc[3][2] = -T(1) / T(2) * (b1 * v - ny / c);
+  Lc[3][3] = T(1) / T(2) * b1;
+}
+
+// Per-field global alphas of a 2D state: x sweep max |u - c|, |u|, |u|, |u + c| (a[0..3]),
+// y sweep max |v - c|, |v|, |v|, |v + c| (a[4..7]).
+static void lf_alpha_2d_char(int64_t N, const double* u, const Phys& ph, double* a8) {
+  double m0 = 0, m1 = 0, m2 = 0, m3 = 0, m4 = 0, m5 = 0;
+#pragma omp parallel for reduction(max : m0, m1, m2, m3, m4, m5)
+  for (int64_t k = 0; k < N; ++k) {
+    const double rho = u[k], mx = u[N + k], my = u[2 * N + k], E = u[3 * N + k];
+    const double uu = mx / rho, vv = my / rho;
+    const double p = (ph.gamma - 1.0) * (E - rho / 2.0 * (uu * uu + vv * vv));
+    const double c = std::sqrt(ph.gamma * p / rho);
+    m0 = std::max(m0, std::fabs(uu - c));
+    m1 = std::max(m1, std::fabs(uu));
+    m2 = std::max(m2, std::fabs(uu + c));
+    m3 = std::max(m3, std::fabs(vv - c));
+    m4 = std::max(m4, std::fabs(vv));
+    m5 = std::max(m5, std::fabs(vv + c));
+  }
+  a8[0] = m0; a8[1] = m1; a8[2] = m1; a8[3] = m2;
+  a8[4] = m3; a8[5] = m4; a8[6] = m4; a8[7] = m5;
+}
+
+// One characteristic sweep along a line of n cells (stride `st` in the state arrays, plane N):
+// adds -(fhat_{i+1/2} - fhat_{i-1/2}) / h to dudt along the line.
+template <class T>
+static void char_sweep_2d(int bc, int dir, int64_t n, int64_t base, int64_t st, int64_t N,
+                          const T* u, T* dudt, T h, const double* a4, const OrcParams& P,
+                          const Phys& ph) {
+  const int64_t np = n + 6;
+  std::vector<T> Up(4 * np), Fp(4 * np), fh(4 * (n + 1));
+  for (int64_t g = -3; g < n + 3; ++g) {
+    const int64_t gi = ghost_index(g, n, bc);
+    T U[4], F[4], G[4];
+    for (int v = 0; v < 4; ++v) U[v] = u[v * N + base + gi * st];
+    euler2_flux(U, F, G, ph);
+    for (int v = 0; v < 4; ++v) {
+      Up[v * np + g + 3] = U[v];
+      Fp[v * np + g + 3] = dir == 0 ? F[v] : G[v];
+    }
+  }
+  for (int64_t k = 0; k <= n; ++k) {
+    const int64_t i = k - 1 + 3;
+    T UL[4], UR[4];
+    for (int v = 0; v < 4; ++v) { UL[v] = Up[v * np + i]; UR[v] = Up[v * np + i + 1]; }
+    T R[4][4], Lc[4][4];
+    roe_eigen_2d(UL, UR, dir, ph, R, Lc);
+    T gp[4][6], gm[4][6];
+    for (int j = 0; j < 6; ++j) {
+      const int64_t cj = i - 2 + j;
+      for (int f = 0; f < 4; ++f) {
+        T V = T(0), G = T(0);
+        for (int v = 0; v < 4; ++v) {
+          V = V + Lc[f][v] * Up[v * np + cj];
+          G = G + Lc[f][v] * Fp[v * np + cj];
+        }
+        gp[f][j] = T(1) / T(2) * (G + T(a4[f]) * V);
+        gm[f][j] = T(1) / T(2) * (G - T(a4[f]) * V);
+      }
+    }
+    T gh[4];
+    for (int f = 0; f < 4; ++f) {
+      T hp = reconstruct(gp[f][0], gp[f][1], gp[f][2], gp[f][3], gp[f][4], P).fhat;
+      T hm = reconstruct(gm[f][5], gm[f][4], gm[f][3], gm[f][2], gm[f][1], P).fhat;
+      gh[f] = hp + hm;
+    }
+    for (int v = 0; v < 4; ++v) {
+      T s = T(0);
+      for (int f = 0; f < 4; ++f) s = s + R[v][f] * gh[f];
+      fh[v * (n + 1) + k] = s;
+    }
+  }
+  for (int v = 0; v < 4; ++v)
+    for (int64_t i = 0; i < n; ++i)
+      dudt[v * N + base + i * st] += -(fh[v * (n + 1) + i + 1] - fh[v * (n + 1) + i]) / h;
+}
+
+template <class T>
+static void rhs_2d_char(int bcx, int bcy, int64_t nx, int64_t ny, const T* u, T* dudt, T dx,
+                        T dy, const double* a8, const OrcParams& P, const Phys& ph) {
+  const int64_t N = nx * ny;
+  for (int64_t k = 0; k < 4 * N; ++k) dudt[k] = T(0);
+#pragma omp parallel for
+  for (int64_t j = 0; j < ny; ++j)
+    char_sweep_2d<T>(bcx, 0, nx, j * nx, 1, N, u, dudt, dx, a8, P, ph);
+#pragma omp parallel for
+  for (int64_t i = 0; i < nx; ++i)
+    char_sweep_2d<T>(bcy, 1, ny, i, nx, N, u, dudt, dy, a8 + 4, P, ph);
+}
+
 // ---------------------------------------------------------------- TVD-RK3
 // Shu-Osher third-order TVD Runge-Kutta (cited in Sec. 4; standard form):
 //   U1 = U^n + dt L(U^n)
@@ -744,6 +887,57 @@ void orc_rk3_run_1d_char_f64(int bc, int64_t n, double* u, double dx, double cfl
       for (int64_t k = 0; k < M; ++k)
         us[k] = RK_A[s] * un[k] + RK_B[s] * (us[k] + dt * L[k]);
       if (alpha_out) for (int f = 0; f < 3; ++f) alpha_out[9 * st + 3 * s + f] = a3[f];
+    }
+    std::memcpy(u, us.data(), sizeof(double) * M);
+    if (dt_out) dt_out[st] = dt;
+  }
+}
+
+// ---- 2D Euler in local characteristic fields (fp64).  alpha8_in: NULL -> the per-field
+// global alphas of u (x sweep a[0..3], y sweep a[4..7]); alpha8_out (may be NULL) receives
+// the alphas used.
+void orc_rhs_2d_char_f64(int bcx, int bcy, int64_t nx, int64_t ny, const double* u,
+                         double* dudt, double dx, double dy, const double* alpha8_in,
+                         const OrcParams* P, double gamma, double* alpha8_out) {
+  Phys ph{0.0, gamma};
+  double a8[8];
+  if (alpha8_in) for (int f = 0; f < 8; ++f) a8[f] = alpha8_in[f];
+  else lf_alpha_2d_char(nx * ny, u, ph, a8);
+  rhs_2d_char<double>(bcx, bcy, nx, ny, u, dudt, dx, dy, a8, *P, ph);
+  if (alpha8_out) for (int f = 0; f < 8; ++f) alpha8_out[f] = a8[f];
+}
+
+// The 2D eigenvector matrices along dir (0: x, 1: y) at the Roe average (row-major R, Lc).
+void orc_roe_eigen_2d_f64(const double* UL, const double* UR, int dir, double gamma,
+                          double* R16, double* L16) {
+  Phys ph{0.0, gamma};
+  double R[4][4], Lc[4][4];
+  roe_eigen_2d(UL, UR, dir, ph, R, Lc);
+  for (int r = 0; r < 4; ++r)
+    for (int c = 0; c < 4; ++c) { R16[4 * r + c] = R[r][c]; L16[4 * r + c] = Lc[r][c]; }
+}
+
+// ---- nsteps TVD-RK3 steps of the 2D characteristic scheme, in place; dt as in
+// orc_rk3_run_2d_f64 (Sec. 4.4), per-field alphas recomputed for every stage.
+void orc_rk3_run_2d_char_f64(int bcx, int bcy, int64_t nx, int64_t ny, double* u, double dx,
+                             double dy, double cfl, int32_t nsteps, const double* dt_in,
+                             const OrcParams* P, double gamma, double* dt_out) {
+  Phys ph{0.0, gamma};
+  const int64_t M = 4 * nx * ny;
+  std::vector<double> un(M), us(M), L(M);
+  for (int32_t st = 0; st < nsteps; ++st) {
+    std::memcpy(un.data(), u, sizeof(double) * M);
+    std::memcpy(us.data(), u, sizeof(double) * M);
+    double sx, sy;
+    lf_alpha_2d(nx * ny, u, ph, &sx, &sy);
+    const double dtx = dx / sx, dty = dy / sy;
+    const double dt = dt_in ? dt_in[st] : cfl * dtx * dty / (dtx + dty);
+    for (int s = 0; s < 3; ++s) {
+      double a8[8];
+      lf_alpha_2d_char(nx * ny, us.data(), ph, a8);
+      rhs_2d_char<double>(bcx, bcy, nx, ny, us.data(), L.data(), dx, dy, a8, *P, ph);
+      for (int64_t k = 0; k < M; ++k)
+        us[k] = RK_A[s] * un[k] + RK_B[s] * (us[k] + dt * L[k]);
     }
     std::memcpy(u, us.data(), sizeof(double) * M);
     if (dt_out) dt_out[st] = dt;
