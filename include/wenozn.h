@@ -254,6 +254,37 @@ int32_t wzn_rk3_step_2d(const wzn_params* p, void* u, void* stage, int64_t nx, i
                         double dx, double dy, double cfl, const double* dt_in, double* dt_out,
                         void* ws, void* stream);
 
+/* ---------------------------------------------------------------- 2D, characteristic fields
+ * The 2D scheme above with each sweep's reconstruction in local characteristic fields: the
+ * procedure of Sec. 4.3 (wzn_rhs_1d_char) applied along x and along y.  At each interface the
+ * flux Jacobian along the sweep is taken at the Roe average of the two neighbouring states
+ * (u, v, H weighted by sqrt(rho)); its eigenvalues are u_n - c, u_n, u_n, u_n + c.  The six
+ * stencil cells are projected with its left eigenvectors and split field by field with the
+ * Lax-Friedrichs alphas alpha_k = max over the cells of |lambda_k| (x sweep: |u - c|, |u|, |u|,
+ * |u + c|; y sweep: the same with v), reconstructed with WENO-ZN and mapped back with the
+ * right eigenvectors.  fp64 only, p->flux_split must be WZN_SPLIT_LF and p->weights
+ * WZN_WEIGHTS_ZN (else WZN_ERR_DTYPE / WZN_ERR_UNSUPPORTED).
+ *
+ * work: device scratch of wzn_char2d_work_doubles(nx, ny) doubles (three states: the x part
+ * of L, the transposed state and the transposed y part), distinct from the other arrays. */
+int64_t wzn_char2d_work_doubles(int64_t nx, int64_t ny);
+
+/* wzn_rhs_2d_char: dudt = L(u) for u[4][ny][nx].  alpha8: NULL (reduced from u, or the
+ * constants p->lf_alpha_x / p->lf_alpha_y for every field when both are >= 0) or a device
+ * array of 8 frozen alphas, the four fields of the x sweep then the four of the y sweep. */
+int32_t wzn_rhs_2d_char(const wzn_params* p, const void* u, void* dudt, void* work, int64_t nx,
+                        int64_t ny, double dx, double dy, const double* alpha8, void* ws,
+                        void* stream);
+
+/* wzn_rk3_run_2d_char: advance u[4][ny][nx] in place by `nsteps` TVD-RK3 steps of the
+ * characteristic scheme; stage: device scratch of 2 * 4 * nx * ny doubles; dt as in
+ * wzn_rk3_run_2d (dt_in / dt_out as there).  The alphas are reduced from every stage input
+ * (p->lf_alpha_x and p->lf_alpha_y must be < 0).  Enqueued as 2 + 15 * nsteps kernels with
+ * no host synchronisation. */
+int32_t wzn_rk3_run_2d_char(const wzn_params* p, void* u, void* stage, void* work, int64_t nx,
+                            int64_t ny, double dx, double dy, double cfl, int32_t nsteps,
+                            const double* dt_in, double* dt_out, void* ws, void* stream);
+
 /* ---------------------------------------------------------------- batched 1D Euler
  * Many independent 1D Euler problems of uneven length, advanced by `nsteps` TVD-RK3 steps in
  * ONE persistent kernel launch (plus a one-word counter reset).  Instance i occupies cells

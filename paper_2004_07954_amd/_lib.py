@@ -53,6 +53,10 @@ SIGNATURES = [
     ("wzn_rk3_step_1d", _I32, [_PP, _P, _P, _I64, _D, _D, _P, _P, _P, _P]),
     ("wzn_rhs_1d_char", _I32, [_PP, _P, _P, _I64, _D, _P, _P, _P]),
     ("wzn_rk3_run_1d_char", _I32, [_PP, _P, _P, _I64, _D, _D, _I32, _P, _P, _P, _P, _P, _P]),
+    ("wzn_char2d_work_doubles", _I64, [_I64, _I64]),
+    ("wzn_rhs_2d_char", _I32, [_PP, _P, _P, _P, _I64, _I64, _D, _D, _P, _P, _P]),
+    ("wzn_rk3_run_2d_char", _I32, [_PP, _P, _P, _P, _I64, _I64, _D, _D, _D, _I32, _P, _P, _P,
+                                   _P]),
     ("wzn_rhs_2d", _I32, [_PP, _P, _P, _I64, _I64, _D, _D, _P, _P]),
     ("wzn_speed_max_2d", _I32, [_PP, _P, _I64, _I64, _P, _P, _P]),
     ("wzn_rhs_2d_strip", _I32, [_PP, _P, _P, _P, _P, _I64, _I64, _D, _D, _P, _P, _P]),

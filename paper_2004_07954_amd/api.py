@@ -321,6 +321,57 @@ def rk3_run_2d(u, dx, dy, nsteps, cfl=0.5, prm=None, dt=None, stage=None, record
     return dt_o
 
 
+def _char2d_work(u, work):
+    need = lib().wzn_char2d_work_doubles(u.shape[2], u.shape[1])
+    if work is None:
+        return torch.empty(need, dtype=torch.float64, device=u.device)
+    if (work.dtype != torch.float64 or work.device != u.device or not work.is_contiguous()
+            or work.numel() < need):
+        raise ValueError("work must be a contiguous fp64 tensor of %d elements" % need)
+    return work
+
+
+def rhs_2d_char(u, dx, dy, prm=None, alpha8=None, out=None, work=None):
+    """L(u) for u[4, ny, nx] (fp64) with each sweep's reconstruction in local characteristic
+    fields.  alpha8: None (reduced from u) or 8 frozen alphas (x sweep's four fields, then the
+    y sweep's) as a float64 tensor or sequence."""
+    _check_state_2d(u)
+    prm = _params_2d(prm, u)
+    al = _dev_f64(alpha8, 8, "alpha8", u.device)
+    out = torch.empty_like(u) if out is None else out
+    _check_state_2d(out, "out")
+    work = _char2d_work(u, work)
+    check(lib().wzn_rhs_2d_char(C.byref(prm), _ptr(u), _ptr(out), _ptr(work), u.shape[2],
+                                u.shape[1], float(dx), float(dy), _ptr(al),
+                                _ptr(workspace(u.device)), _stream()))
+    return out
+
+
+def rk3_run_2d_char(u, dx, dy, nsteps, cfl=0.5, prm=None, dt=None, stage=None, work=None,
+                    record=False):
+    """Advance u[4, ny, nx] (fp64) in place by nsteps TVD-RK3 steps of the characteristic
+    scheme; record=True returns the dt history (device tensor [nsteps])."""
+    _check_state_2d(u)
+    prm = _params_2d(prm, u)
+    if stage is None:
+        stage = torch.empty((2,) + tuple(u.shape), dtype=u.dtype, device=u.device)
+    if stage.numel() < 2 * u.numel() or not stage.is_contiguous() or stage.dtype != u.dtype:
+        raise ValueError("stage must be a contiguous tensor of 2 * u.numel() elements")
+    work = _char2d_work(u, work)
+    if dt is None:
+        dt_t = None
+    elif isinstance(dt, (int, float)):
+        dt_t = torch.full((nsteps,), float(dt), dtype=torch.float64, device=u.device)
+    else:
+        dt_t = _dev_f64(dt, nsteps, "dt", u.device)
+    dt_o = torch.empty(nsteps, dtype=torch.float64, device=u.device) if record else None
+    check(lib().wzn_rk3_run_2d_char(C.byref(prm), _ptr(u), _ptr(stage), _ptr(work), u.shape[2],
+                                    u.shape[1], float(dx), float(dy), float(cfl), int(nsteps),
+                                    _ptr(dt_t), _ptr(dt_o), _ptr(workspace(u.device)),
+                                    _stream()))
+    return dt_o
+
+
 def batch_tuning(nt=128, k=2, blocks_per_cu=0, layout=0):
     return _lib.WznBatchTuning(int(nt), int(k), int(blocks_per_cu), int(layout))
 

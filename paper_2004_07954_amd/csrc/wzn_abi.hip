@@ -374,6 +374,56 @@ int32_t wzn_rk3_run_2d(const wzn_params* p, void* u, void* stage, int64_t nx, in
   return scanned(st, p, u, 4 * nx * ny, f32, &w, stream);
 }
 
+int64_t wzn_char2d_work_doubles(int64_t nx, int64_t ny) {
+  return nx > 0 && ny > 0 ? 12 * nx * ny : 0;
+}
+
+static int check_char2d(const wzn_params* p, int64_t nx, int64_t ny, double dx, double dy,
+                        void* ws, const void* work) {
+  int st = check_2d(p, nx, ny, dx, dy, ws);
+  if (st) return st;
+  if (p->dtype != WZN_FP64)
+    return set_error(WZN_ERR_DTYPE, "characteristic fields run in fp64 only");
+  if (p->flux_split != WZN_SPLIT_LF)
+    return set_error(WZN_ERR_UNSUPPORTED, "characteristic fields use the Lax-Friedrichs split");
+  if (p->weights != WZN_WEIGHTS_ZN)
+    return set_error(WZN_ERR_UNSUPPORTED, "characteristic fields run the WENO-ZN weights");
+  if (!work) return set_error(WZN_ERR_ARG, "work is NULL");
+  return WZN_OK;
+}
+
+int32_t wzn_rhs_2d_char(const wzn_params* p, const void* u, void* dudt, void* work, int64_t nx,
+                        int64_t ny, double dx, double dy, const double* alpha8, void* ws,
+                        void* stream) {
+  g_err[0] = 0;
+  int st = check_char2d(p, nx, ny, dx, dy, ws, work);
+  if (st) return st;
+  if (!u || !dudt) return set_error(WZN_ERR_ARG, "u or dudt is NULL");
+  if (u == dudt || work == u || work == dudt)
+    return set_error(WZN_ERR_ARG, "u, dudt and work must not alias");
+  Workspace w = make_workspace(ws);
+  return scanned(rhs_2d_char(p, (const double*)u, (double*)dudt, (double*)work, nx, ny, dx, dy,
+                             alpha8, &w, (hipStream_t)stream),
+                 p, dudt, 4 * nx * ny, false, &w, stream);
+}
+
+int32_t wzn_rk3_run_2d_char(const wzn_params* p, void* u, void* stage, void* work, int64_t nx,
+                            int64_t ny, double dx, double dy, double cfl, int32_t nsteps,
+                            const double* dt_in, double* dt_out, void* ws, void* stream) {
+  g_err[0] = 0;
+  int st = check_char2d(p, nx, ny, dx, dy, ws, work);
+  if (st) return st;
+  if (!u || !stage) return set_error(WZN_ERR_ARG, "u or stage is NULL");
+  if (work == u || work == stage || stage == u)
+    return set_error(WZN_ERR_ARG, "u, stage and work must not alias");
+  if (nsteps < 0) return set_error(WZN_ERR_ARG, "nsteps < 0");
+  if (!dt_in && !(cfl > 0.0)) return set_error(WZN_ERR_ARG, "cfl must be positive");
+  Workspace w = make_workspace(ws);
+  return scanned(rk3_run_2d_char(p, (double*)u, (double*)stage, (double*)work, nx, ny, dx, dy,
+                                 cfl, nsteps, dt_in, dt_out, &w, (hipStream_t)stream),
+                 p, u, 4 * nx * ny, false, &w, stream);
+}
+
 int32_t wzn_rk3_step_2d(const wzn_params* p, void* u, void* stage, int64_t nx, int64_t ny,
                         double dx, double dy, double cfl, const double* dt_in, double* dt_out,
                         void* ws, void* stream) {

@@ -77,6 +77,13 @@ int rk3_run_1d_char(const wzn_params* p, double* u, double* stage, int64_t n, do
                     double cfl, int32_t nsteps, const double* dt_in, const double* alpha_in,
                     double* dt_out, double* alpha_out, Workspace* ws, hipStream_t s);
 
+int rhs_2d_char(const wzn_params* p, const double* u, double* dudt, double* work, int64_t nx,
+                int64_t ny, double dx, double dy, const double* alpha8, Workspace* ws,
+                hipStream_t s);
+int rk3_run_2d_char(const wzn_params* p, double* u, double* stage, double* work, int64_t nx,
+                    int64_t ny, double dx, double dy, double cfl, int32_t nsteps,
+                    const double* dt_in, double* dt_out, Workspace* ws, hipStream_t s);
+
 int rhs_1d_vjp(const wzn_params* p, const double* u, const double* mu, double* out, int64_t n,
                double dx, Workspace* ws, hipStream_t s);
 int rk3_step_1d_vjp(const wzn_params* p, const double* stages, const double* lam_next,
