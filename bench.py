@@ -268,6 +268,35 @@ def bench_char(n, steps, warmup=3, cpu_steps=3):
     return rec
 
 
+def bench_char2d(steps, warmup=3):
+    """Secondary figure: 2D Euler with each sweep's reconstruction in local characteristic
+    fields (the 1D procedure of Sec. 4.3 along x and y), on the paper's second Riemann case at
+    2400^2, transmissive, CFL 0.5, fp64.  One stage = the x sweep, two transposes, the y sweep
+    of the transposed state and the finish kernel."""
+    import torch
+    from paper_2004_07954_amd import api, inputs as I
+    nx = ny = 2400
+    u0, dx, dy = I.riemann_2d(2, nx)
+    u0t = torch.tensor(u0, dtype=torch.float64, device="cuda")
+    u = u0t.clone()
+    stage = torch.empty((2, 4, ny, nx), dtype=torch.float64, device="cuda")
+    work = torch.empty(12 * nx * ny, dtype=torch.float64, device="cuda")
+    api.rk3_run_2d_char(u, dx, dy, warmup, stage=stage, work=work)
+    u.copy_(u0t)
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    api.rk3_run_2d_char(u, dx, dy, steps, stage=stage, work=work)
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e)
+    assert torch.isfinite(u).all().item()
+    return {"workload": "euler2d_riemann_case2_characteristic_%dx%d" % (nx, ny), "dtype": "f64",
+            "steps": steps, "ms_per_step": ms / steps,
+            "value": nx * ny * 3 * steps / (ms * 1e-3), "unit": "cell-RHS/s",
+            "stage_ms": ms / (3 * steps)}
+
+
 def bench_strip(evals=100):
     """Secondary figure: one GPU's share of a row decomposition of the 4096^2 grid over eight
     GPUs, a 4096 x 512 strip (fp64, Lax-Friedrichs), its right-hand side with ghost rows and
@@ -411,6 +440,9 @@ def main():
     ap.add_argument("--no-strip", action="store_true",
                     help="skip the one-share-of-eight 2D strip figure")
     ap.add_argument("--no-large", action="store_true", help="skip the 1D N = 2^25 figure")
+    ap.add_argument("--no-char2d", action="store_true",
+                    help="skip the 2D characteristic-field figure")
+    ap.add_argument("--steps-char2d", type=int, default=100)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed region, copy 256 MiB with a plain torch copy "
                          "(reference kernel for rocprof FETCH_SIZE / WRITE_SIZE scaling)")
@@ -548,6 +580,9 @@ def main():
         log("characteristic fields, N =", n)
         rec.setdefault("secondary", {})["characteristic"] = bench_char(
             n, args.steps_char, cpu_steps=0 if args.no_cpu_baseline else 3)
+    if not args.no_char2d:
+        log("2D characteristic fields, 2400^2")
+        rec.setdefault("secondary", {})["characteristic_2d"] = bench_char2d(args.steps_char2d)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         rec["cpu_baseline"] = cpu_baseline(n)

@@ -15,9 +15,10 @@
 // The y sweep is the same kernel on the transposed state with the two momenta exchanged:
 // the y Jacobian of U is the x Jacobian of the exchanged state, and the exchange flips only
 // the sign of the shear eigenvector, which cancels in R ghat because the reconstruction is an
-// odd function of its data.  One right-hand side is: x sweep -> Lx; transpose U -> Ut; x sweep
-// of Ut -> Lyt; transpose Lyt -> Ly; finish: L = Lx + Ly, or the TVD-RK3 stage combination,
-// with the per-field maxima of the output for the next stage's alphas and the next step's dt.
+// odd function of its data.  One right-hand side is: transpose U -> Ut; x sweep of Ut -> Lyt;
+// transpose Lyt -> Ly; then the x sweep of U, whose epilogue adds Ly and writes L, or the
+// TVD-RK3 stage combination (U from LDS) with the per-field maxima of the output for the next
+// stage's alphas and the next step's dt.
 #include <hip/hip_runtime.h>
 
 #include "wzn_device.hpp"
@@ -42,6 +43,19 @@ struct Char2Args {
   double alpha_const;
   unsigned long long* slot_zero;  // words cleared by workgroup 0, or null
   int zero_count;
+  // FUSE (the x sweep): the epilogue adds ly [4][rows][n] (the y part of L) and writes L
+  // (MODE_RHS) or the TVD-RK3 stage output, with the per-field maxima of the output
+  const double* ly;
+  const double* un;    // U^n or null
+  int mode;
+  double rk_a, rk_b;
+  const double* dt_arr;                   // dt: array /
+  const unsigned long long* dt_speed_slot;  // cfl dtx dty / (dtx + dty) from six slots /
+  const double* dt_slot_read;             // the dt slot
+  double cfl, dx, dy;
+  double* dt_slot_write;
+  double* dt_rec;
+  unsigned long long* speed_next;  // [6] maxima of the output, or null
 };
 
 // staged per-cell planes
@@ -52,7 +66,11 @@ constexpr int C2_NT = 256;
 // one interface).  Every cell of the tile and its halo is loaded once and its U, F, sqrt(rho),
 // u, v and H are staged in LDS; each thread builds the Roe eigen-system of its interface and
 // reconstructs the four fields one after another, re-reading the stencil from LDS for each.
-template <int NT>
+__device__ __forceinline__ void char2_speeds(double rho, double mx, double my, double E,
+                                             double gamma, double (&s)[6]);
+__device__ __forceinline__ void block_max6(double (&s)[6], unsigned long long* slot);
+
+template <int NT, bool FUSE>
 __global__ __launch_bounds__(NT) void char2_kernel(Char2Args a) {
   constexpr int NC = NT + 5;  // cells c0 - 3 .. c0 + NT + 1
   __shared__ double S[C2_N][NC];
@@ -98,6 +116,21 @@ __global__ __launch_bounds__(NT) void char2_kernel(Char2Args a) {
     S[C2_VU][l] = u;
     S[C2_VV][l] = v;
     S[C2_H][l] = (E + p) * r;
+  }
+  // (FUSE) the epilogue's loads of the y part and of U^n are issued now, so that they are in
+  // flight during the reconstructions
+  const int i = c0 + tid;
+  const bool owns = tid < NT - 1 && i < a.n;
+  const int64_t gi = row * a.n + (owns ? i : 0);
+  double lyv[4] = {0.0, 0.0, 0.0, 0.0}, unv[4] = {0.0, 0.0, 0.0, 0.0};
+  if constexpr (FUSE) {
+    if (owns) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        lyv[v] = a.ly[v * a.plane + gi];
+        if (a.un) unv[v] = a.un[v * a.plane + gi];
+      }
+    }
   }
   __syncthreads();
 
@@ -159,11 +192,57 @@ __global__ __launch_bounds__(NT) void char2_kernel(Char2Args a) {
   __syncthreads();
 
   // ---- output cell c0 + t: faces t (left) and t + 1 (right); FH holds twice the flux
-  const int i = c0 + tid;
-  if (tid < NT - 1 && i < a.n) {
-    double* out = a.out + row * a.n + i;
+  if constexpr (!FUSE) {
+    (void)lyv;
+    (void)unv;
+    if (owns) {
+      double* out = a.out + row * a.n + i;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) out[v * a.plane] = (FH[v][tid] - FH[v][tid + 1]) * a.half_inv_h;
+      for (int v = 0; v < 4; ++v)
+        out[v * a.plane] = (FH[v][tid] - FH[v][tid + 1]) * a.half_inv_h;
+    }
+  } else {
+    double dt = 0.0;
+    if (a.mode == MODE_STAGE) {
+      if (a.dt_arr) {
+        dt = a.dt_arr[0];
+      } else if (a.dt_speed_slot) {
+        // max(|u - c|, |u + c|) is |u| + c bit for bit, likewise for v
+        const double sx = fmax(slot_value(a.dt_speed_slot), slot_value(a.dt_speed_slot + 2));
+        const double sy =
+            fmax(slot_value(a.dt_speed_slot + 3), slot_value(a.dt_speed_slot + 5));
+        const double dtx = a.dx / sx, dty = a.dy / sy;
+        dt = a.cfl * dtx * dty / (dtx + dty);
+      } else {
+        dt = a.dt_slot_read[0];
+      }
+    }
+    if (blockIdx.x == 0 && tid == 0) {
+      if (a.dt_slot_write) a.dt_slot_write[0] = dt;
+      if (a.dt_rec) a.dt_rec[0] = dt;
+    }
+    double m[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (owns) {
+      // (no contraction: the x part is rounded before the y part is added, as the y part
+      // was, so that exchanging x and y gives the same bits)
+#pragma clang fp contract(off)
+      double o[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double lxv = (FH[v][tid] - FH[v][tid + 1]) * a.half_inv_h;
+        const double L = lxv + lyv[v];
+        if (a.mode == MODE_RHS) {
+          o[v] = L;
+        } else {
+          double base = a.rk_b * S[C2_U0 + v][tid + 3];
+          if (a.un) base = fma_t(a.rk_a, unv[v], base);
+          o[v] = fma_t(a.rk_b * dt, L, base);
+        }
+        a.out[v * a.plane + gi] = o[v];
+      }
+      if (a.speed_next) char2_speeds(o[0], o[1], o[2], o[3], a.gamma, m);
+    }
+    if (a.speed_next) block_max6(m, a.speed_next);
   }
 }
 
@@ -235,78 +314,13 @@ __global__ __launch_bounds__(256) void char2_speed_kernel(const double* __restri
   block_max6(m, slot);
 }
 
-struct Char2Finish {
-  const double* lx;    // [4][N]
-  const double* ly;    // [4][N]
-  const double* uin;   // stage input
-  const double* un;    // U^n or null
-  double* out;         // L (MODE_RHS) or U^(s+1)
-  int64_t N;
-  int mode;
-  double rk_a, rk_b;
-  // dt: array / cfl dtx dty / (dtx + dty) from the six slots of U^n / the dt slot
-  const double* dt_arr;
-  const unsigned long long* dt_speed_slot;
-  const double* dt_slot_read;
-  double cfl, dx, dy;
-  double* dt_slot_write;
-  double* dt_rec;
-  double gamma;
-  unsigned long long* speed_next;  // [6] maxima of the output, or null
-};
-
-__global__ __launch_bounds__(256) void char2_finish_kernel(Char2Finish a) {
-  double dt = 0.0;
-  if (a.mode == MODE_STAGE) {
-    if (a.dt_arr) {
-      dt = a.dt_arr[0];
-    } else if (a.dt_speed_slot) {
-      // max(|u - c|, |u + c|) is |u| + c bit for bit, likewise for v
-      const double sx = fmax(slot_value(a.dt_speed_slot), slot_value(a.dt_speed_slot + 2));
-      const double sy = fmax(slot_value(a.dt_speed_slot + 3), slot_value(a.dt_speed_slot + 5));
-      const double dtx = a.dx / sx, dty = a.dy / sy;
-      dt = a.cfl * dtx * dty / (dtx + dty);
-    } else {
-      dt = a.dt_slot_read[0];
-    }
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    if (a.dt_slot_write) a.dt_slot_write[0] = dt;
-    if (a.dt_rec) a.dt_rec[0] = dt;
-  }
-  const double cdt = a.rk_b * dt;
-  double m[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < a.N;
-       k += (int64_t)gridDim.x * 256) {
-    double o[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const double L = a.lx[v * a.N + k] + a.ly[v * a.N + k];
-      if (a.mode == MODE_RHS) {
-        o[v] = L;
-      } else {
-        double base = a.rk_b * a.uin[v * a.N + k];
-        if (a.un) base = fma_t(a.rk_a, a.un[v * a.N + k], base);
-        o[v] = fma_t(cdt, L, base);
-      }
-      a.out[v * a.N + k] = o[v];
-    }
-    if (a.speed_next) {
-      double s[6];
-      char2_speeds(o[0], o[1], o[2], o[3], a.gamma, s);
-#pragma unroll
-      for (int f = 0; f < 6; ++f) m[f] = fmax(m[f], s[f]);
-    }
-  }
-  if (a.speed_next) block_max6(m, a.speed_next);
-}
-
 // ------------------------------------------------------------------ host side
+template <bool FUSE>
 static int launch_char2(Char2Args a, hipStream_t s) {
   a.tiles = ((int64_t)a.n + C2_NT - 2) / (C2_NT - 1);
   const int64_t blocks = a.tiles * a.rows;
   if (blocks > 0x7fffffff) return set_error(WZN_ERR_SIZE, "grid too large (characteristic sweep)");
-  hipLaunchKernelGGL((char2_kernel<C2_NT>), dim3((unsigned)blocks), dim3(C2_NT), 0, s, a);
+  hipLaunchKernelGGL((char2_kernel<C2_NT, FUSE>), dim3((unsigned)blocks), dim3(C2_NT), 0, s, a);
   return check_launch("char2_kernel");
 }
 
@@ -319,22 +333,12 @@ static int launch_transpose_swap(const double* src, double* dst, int64_t R, int6
   return check_launch("transpose_swap_kernel");
 }
 
-static int64_t grid_stride_blocks(int64_t N) {
-  int64_t b = (N + 255) / 256;
-  return b > 4096 ? 4096 : (b < 1 ? 1 : b);
-}
-
 static int launch_char2_speed(const double* u, int64_t N, double gamma,
                               unsigned long long* slot, hipStream_t s) {
-  hipLaunchKernelGGL(char2_speed_kernel, dim3((unsigned)grid_stride_blocks(N)), dim3(256), 0, s,
-                     u, N, gamma, slot);
+  int64_t b = (N + 255) / 256;
+  b = b > 4096 ? 4096 : (b < 1 ? 1 : b);
+  hipLaunchKernelGGL(char2_speed_kernel, dim3((unsigned)b), dim3(256), 0, s, u, N, gamma, slot);
   return check_launch("char2_speed_kernel");
-}
-
-static int launch_char2_finish(const Char2Finish& f, hipStream_t s) {
-  hipLaunchKernelGGL(char2_finish_kernel, dim3((unsigned)grid_stride_blocks(f.N)), dim3(256), 0,
-                     s, f);
-  return check_launch("char2_finish_kernel");
 }
 
 static Char2Args char2_base(const wzn_params* p, int64_t n, int64_t rows, double h, int bc) {
@@ -362,38 +366,29 @@ static void set_alpha(Char2Args& a, const wzn_params* p, const Char2Alpha& al, i
   else a.alpha_const = dir == 0 ? p->lf_alpha_x : p->lf_alpha_y;
 }
 
-// One right-hand side L(U) into lx (x part) and, through the transposes, ly; work holds
-// three states: [0] Lx, [1] the transposed state, then Ly, [2] the transposed y part.
-static int char2_parts(const wzn_params* p, const double* u, double* work, int64_t nx,
-                       int64_t ny, double dx, double dy, const Char2Alpha& al,
-                       unsigned long long* zero6, hipStream_t s, double** lx, double** ly) {
+// The y part of L(U) over the untransposed grid, into work[0 .. 4 nx ny): work holds three
+// states, [0] the y part, [1] the transposed state, [2] its x-sweep part.  The y sweep's
+// workgroup 0 clears the six words zero6 (if given).
+static int char2_ypart(const wzn_params* p, const double* u, double* work, int64_t nx,
+                       int64_t ny, double dy, const Char2Alpha& al, unsigned long long* zero6,
+                       hipStream_t s) {
   const int64_t M = 4 * nx * ny;
-  double* Lx = work;
+  double* Ly = work;
   double* Ut = work + M;
   double* Lyt = work + 2 * M;
-  Char2Args ax = char2_base(p, nx, ny, dx, p->bc_x);
-  ax.uin = u;
-  ax.out = Lx;
-  set_alpha(ax, p, al, 0);
-  if (zero6) {
-    ax.slot_zero = zero6;
-    ax.zero_count = 6;
-  }
-  int st = launch_char2(ax, s);
-  if (st) return st;
-  st = launch_transpose_swap(u, Ut, ny, nx, s);
+  int st = launch_transpose_swap(u, Ut, ny, nx, s);
   if (st) return st;
   Char2Args ay = char2_base(p, ny, nx, dy, p->bc_y);
   ay.uin = Ut;
   ay.out = Lyt;
   set_alpha(ay, p, al, 1);
-  st = launch_char2(ay, s);
+  if (zero6) {
+    ay.slot_zero = zero6;
+    ay.zero_count = 6;
+  }
+  st = launch_char2<false>(ay, s);
   if (st) return st;
-  st = launch_transpose_swap(Lyt, Ut, nx, ny, s);  // Ly over the transposed state
-  if (st) return st;
-  *lx = Lx;
-  *ly = Ut;
-  return WZN_OK;
+  return launch_transpose_swap(Lyt, Ly, nx, ny, s);
 }
 
 int rhs_2d_char(const wzn_params* p, const double* u, double* dudt, double* work, int64_t nx,
@@ -410,23 +405,20 @@ int rhs_2d_char(const wzn_params* p, const double* u, double* dudt, double* work
     if (st) return st;
     al.slot6 = slot;
   }
-  double *lx = nullptr, *ly = nullptr;
-  int st = char2_parts(p, u, work, nx, ny, dx, dy, al, nullptr, s, &lx, &ly);
+  int st = char2_ypart(p, u, work, nx, ny, dy, al, nullptr, s);
   if (st) return st;
-  Char2Finish f{};
-  f.lx = lx;
-  f.ly = ly;
-  f.uin = u;
-  f.out = dudt;
-  f.N = nx * ny;
-  f.mode = MODE_RHS;
-  f.gamma = p->gamma;
-  return launch_char2_finish(f, s);
+  Char2Args ax = char2_base(p, nx, ny, dx, p->bc_x);
+  ax.uin = u;
+  ax.out = dudt;
+  ax.ly = work;
+  ax.mode = MODE_RHS;
+  set_alpha(ax, p, al, 0);
+  return launch_char2<true>(ax, s);
 }
 
 // Slot protocol: a ring of three sets of six words; stage s reads the maxima of its input
-// from set s % 3 (its alphas, and at the first stage of a step the dt speeds), the x sweep
-// clears set (s + 2) % 3, and the finish kernel maxes those of its output into set (s + 1) % 3.
+// from set s % 3 (its alphas, and at the first stage of a step the dt speeds), the y sweep
+// clears set (s + 2) % 3, and the x sweep maxes those of its output into set (s + 1) % 3.
 int rk3_run_2d_char(const wzn_params* p, double* u, double* stage, double* work, int64_t nx,
                     int64_t ny, double dx, double dy, double cfl, int32_t nsteps,
                     const double* dt_in, double* dt_out, Workspace* ws, hipStream_t s) {
@@ -448,39 +440,35 @@ int rk3_run_2d_char(const wzn_params* p, double* u, double* stage, double* work,
   int64_t sidx = 0;
   for (int32_t step = 0; step < nsteps; ++step) {
     for (int k = 0; k < 3; ++k, ++sidx) {
-      double* uin = k == 0 ? u : (k == 1 ? U1 : U2);
+      const double* uin = k == 0 ? u : (k == 1 ? U1 : U2);
       double* out = k == 0 ? U1 : (k == 1 ? U2 : u);
       unsigned long long* cur = ring + 6 * (sidx % 3);
       Char2Alpha al{cur, nullptr};
-      double *lx = nullptr, *ly = nullptr;
-      st = char2_parts(p, uin, work, nx, ny, dx, dy, al, ring + 6 * ((sidx + 2) % 3), s, &lx,
-                       &ly);
+      st = char2_ypart(p, uin, work, nx, ny, dy, al, ring + 6 * ((sidx + 2) % 3), s);
       if (st) return st;
-      Char2Finish f{};
-      f.lx = lx;
-      f.ly = ly;
-      f.uin = uin;
-      f.un = k == 0 ? nullptr : u;
-      f.out = out;
-      f.N = N;
-      f.mode = MODE_STAGE;
-      f.rk_a = RA[k];
-      f.rk_b = RB[k];
-      f.gamma = p->gamma;
+      Char2Args ax = char2_base(p, nx, ny, dx, p->bc_x);
+      ax.uin = uin;
+      ax.out = out;
+      ax.ly = work;
+      ax.un = k == 0 ? nullptr : u;
+      ax.mode = MODE_STAGE;
+      ax.rk_a = RA[k];
+      ax.rk_b = RB[k];
+      set_alpha(ax, p, al, 0);
       if (dt_in) {
-        f.dt_arr = dt_in + step;
+        ax.dt_arr = dt_in + step;
       } else if (k == 0) {
-        f.dt_speed_slot = cur;
-        f.cfl = cfl;
-        f.dx = dx;
-        f.dy = dy;
-        f.dt_slot_write = ws->dt;
+        ax.dt_speed_slot = cur;
+        ax.cfl = cfl;
+        ax.dx = dx;
+        ax.dy = dy;
+        ax.dt_slot_write = ws->dt;
       } else {
-        f.dt_slot_read = ws->dt;
+        ax.dt_slot_read = ws->dt;
       }
-      if (dt_out && k == 0) f.dt_rec = dt_out + step;
-      f.speed_next = ring + 6 * ((sidx + 1) % 3);
-      st = launch_char2_finish(f, s);
+      if (dt_out && k == 0) ax.dt_rec = dt_out + step;
+      ax.speed_next = ring + 6 * ((sidx + 1) % 3);
+      st = launch_char2<true>(ax, s);
       if (st) return st;
     }
   }
