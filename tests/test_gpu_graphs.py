@@ -74,6 +74,21 @@ def test_graph_rk3_run_2d(api):
                        ref, lambda: api.rk3_run_1d(other, 0.01, 1))
 
 
+def test_graph_rk3_run_2d_char(api):
+    import torch
+    note("graph: rk3_run_2d_char, 150 x 110, 5 steps")
+    u0, dx, dy = I.riemann_2d(2, 150)
+    u0 = torch.tensor(u0[:, :110, :], dtype=torch.float64, device="cuda").contiguous()
+    stage = torch.empty((2,) + tuple(u0.shape), dtype=torch.float64, device="cuda")
+    work = torch.empty(12 * u0[0].numel(), dtype=torch.float64, device="cuda")
+    u = u0.clone()
+    api.rk3_run_2d_char(u, dx, dy, 5, stage=stage, work=work)
+    ref = u.clone()
+    other = torch.tensor(I.random_smooth_2d(40, 30, seed=5), dtype=torch.float64, device="cuda")
+    _replays_match(lambda t: api.rk3_run_2d_char(t, dx, dy, 5, stage=stage, work=work), u, u0,
+                   ref, lambda: api.rhs_2d_char(other, 0.01, 0.01))
+
+
 def test_graph_batched(api):
     import torch
     note("graph: batched_rk3_run_1d, 96 instances, 10 steps")
