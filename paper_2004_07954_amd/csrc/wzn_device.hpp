@@ -21,7 +21,8 @@
 // Weights (Sec. 3, eq:function and eq:new, normalised as eq:5) are evaluated in the
 // algebraically equal single-divide form: with s_k = IS_k + eps, num = IS0 + IS2 - tau5 + eps,
 // den = tau5 + eps,
-//   alpha_k * den^2 * s0 s1 s2 = c_k * prod_{j != k} s_j * (A num^2 s_k + tau8 den^2) =: c_k B_k
+//   alpha_k * den^2 * s0 s1 s2 = c_k * (A num^2 P + tau8 den^2 pi_k) =: c_k B_k,
+// P = s0 s1 s2, pi_k = prod_{j != k} s_j,
 // and, since sum_k omega_k = 1,
 //   fhat = q1 + (c0 B0 (q0 - q1) + c2 B2 (q2 - q1)) / sum_k c_k B_k
 // with q0 - q1 = (D_m - D_{m+1})/3, q2 - q1 = (D_{m+1} - D_{m+2})/6 and
@@ -66,16 +67,6 @@ __device__ __forceinline__ float rcp_nr(float x) {
   return __builtin_fmaf(e, r, r);
 }
 
-// num / den from one v_rcp (relative error up to ~5e-8) and one correction: with r = rcp(den)
-// and e = 1 - den r, num r (1 + e) has relative error ~e^2 (~2e-15).  Used for the nonlinear
-// correction term of the reconstruction, whose error is relative to itself.
-__device__ __forceinline__ double approx_div(double num, double den) {
-  const double r = __builtin_amdgcn_rcp(den);
-  const double e = __builtin_fma(-den, r, 1.0);
-  const double q = num * r;
-  return __builtin_fma(q, e, q);
-}
-
 // sqrt(x) for x >= 0 from one v_rsq (relative error up to ~5e-8) and one Goldschmidt step:
 // with y = rsq(x), s = x y, h = y / 2, s (1 + (1/2 - s h)) has relative error ~1.5 (s h)^2
 // deviations (~4e-15).  x = 0 gives 0; x < 0 or NaN gives NaN, as sqrt does.
@@ -99,13 +90,16 @@ template <> __device__ __forceinline__ float window_const<float>(double A) { ret
 
 // Aq = window_const<double>(A) = A / 4.  Per window element j the shared quantities are the
 // differences g_j, D_j, e_j = D_j - D_{j+1} and 13/3 D_j^2 + eps (so that each s_k = IS_k + eps
-// is one fma); per interface: tau5 = |s0 - s2|, num = (s0 + s2 - tau5) - eps (= IS0 + IS2 - tau5
-// + eps up to rounding, and only num^2 enters C), b = e_m - e_{m+1}, q1 = v_{m+2} + g_{m+2}/2
-// - D_{m+1}/6, q0 - q1 = e_m/3, q2 - q1 = e_{m+1}/6.
+// is one fma); per interface: tau5 = |s0 - s2|, num = 2 min(s0, s2) - eps (s0 + s2 - |s0 - s2|
+// is 2 min(s0, s2), so this is IS0 + IS2 - tau5 + eps up to one rounding; only num^2 enters C),
+// b = e_m - e_{m+1}, q1 = v_{m+2} + g_{m+2}/2 - D_{m+1}/6, q0 - q1 = e_m/3, q2 - q1 = e_{m+1}/6.
+// The quotient of the nonlinear correction comes from one v_rcp_f64 (relative error up to
+// ~5e-8) and one correction folded into the final fma: with r = rcp(S) and e = 1 - S r,
+// fhat = q1 + (nr r)(1 + e), whose correction term has relative error ~e^2 (~2e-15).
 // WT selects the nonlinear weights: WEIGHTS_ZN, the paper's (Sec. 3, eq:new), or WEIGHTS_Z,
 // the WENO-Z weights with q = 1 the paper compares against (Sec. 2.2, eq:15),
 // alpha_k = c_k (1 + tau5/(IS_k + eps)).  In the product form above the latter is
-// B_k = prod_{j != k} s_j (s_k + tau5) (Aq unused), the same normalisation.
+// B_k = P + tau5 pi_k (Aq unused), the same normalisation.
 enum { WEIGHTS_ZN = 0, WEIGHTS_Z = 1 };
 
 template <int K, int WT = WEIGHTS_ZN>
@@ -129,42 +123,45 @@ __device__ __forceinline__ void wzn_window(const double* v, double* fh, double e
 
 #pragma unroll
   for (int m = 0; m < K; ++m) {
-    const double E0 = __builtin_fma(3.0, g[m + 1], -g[m]);
+    // 3 g_{m+1} - g_m = 2 g_{m+1} + D_m and g_{m+3} - 3 g_{m+2} = D_{m+2} - 2 g_{m+2}: inline
+    // constants, so no operand has to be copied for an accumulating fma
+    const double E0 = __builtin_fma(2.0, g[m + 1], D[m]);
     const double E1 = g[m + 1] + g[m + 2];
-    const double E2 = __builtin_fma(-3.0, g[m + 2], g[m + 3]);
+    const double E2 = __builtin_fma(-2.0, g[m + 2], D[m + 2]);
     const double s0 = __builtin_fma(E0, E0, DD[m]);
     const double s1 = __builtin_fma(E1, E1, DD[m + 1]);
     const double s2 = __builtin_fma(E2, E2, DD[m + 2]);
 
-    const double d = s0 - s2;
-    const double t5 = __builtin_fabs(d);
-    double t0, t1, t2;
+    const double t5 = __builtin_fabs(s0 - s2);
+    const double p0 = s1 * s2, p1 = s0 * s2, p2 = s0 * s1;
+    // B_k = GP + H pi_k
+    double GP, H;
     if constexpr (WT == WEIGHTS_Z) {
-      t0 = s0 + t5;
-      t1 = s1 + t5;
-      t2 = s2 + t5;
+      GP = s0 * p0;
+      H = t5;
     } else {
-      const double num = ((s0 + s2) - t5) - eps_s;
+      const double num = __builtin_fma(2.0, __builtin_fmin(s0, s2), -eps_s);
       const double den = t5 + eps_s;
       // tau8 (in the units of the scaled indicators) = (2 b)^2, b = D_m - 2 D_{m+1} + D_{m+2};
-      // H = tau8 den^2 / 4, G = A num^2 / 4
+      // H = tau8 den^2 / 4, GP = A num^2 P / 4
       const double b = e[m] - e[m + 1];
       const double bd = b * den;
-      const double H = bd * bd;
-      const double G = (Aq * num) * num;
-      t0 = __builtin_fma(G, s0, H);
-      t1 = __builtin_fma(G, s1, H);
-      t2 = __builtin_fma(G, s2, H);
+      H = bd * bd;
+      GP = ((Aq * num) * num) * (s0 * p0);
     }
-    const double B0 = (s1 * s2) * t0;
-    const double B1 = (s0 * s2) * t1;
-    const double B2 = (s0 * s1) * t2;
-    const double S = __builtin_fma(6.0, B1, __builtin_fma(3.0, B2, B0));
-    const double x0 = e[m] * (1.0 / 3.0);
-    const double x2 = e[m + 1] * 0.5;
+    const double B0 = __builtin_fma(H, p0, GP);
+    const double B1 = __builtin_fma(H, p1, GP);
+    const double B2 = __builtin_fma(H, p2, GP);
+    // numerator and denominator / 6: S = B0/6 + B1 + B2/2 accumulates into B1, which nothing
+    // else reads, so no copy of B0 or B2 is needed
+    const double S = __builtin_fma(1.0 / 6.0, B0, __builtin_fma(0.5, B2, B1));
+    const double x0 = e[m] * (1.0 / 18.0);
+    const double x2 = e[m + 1] * (1.0 / 12.0);
     const double nr = __builtin_fma(B0, x0, B2 * x2);
     const double base = __builtin_fma(-1.0 / 6.0, D[m + 1], __builtin_fma(0.5, g[m + 2], v[m + 2]));
-    fh[m] = base + approx_div(nr, S);
+    const double r = __builtin_amdgcn_rcp(S);
+    const double ope = __builtin_fma(-S, r, 2.0);  // 1 + e
+    fh[m] = __builtin_fma(nr * r, ope, base);
   }
 }
 
