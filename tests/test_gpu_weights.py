@@ -168,3 +168,23 @@ def test_reconstruct_sizes(api):
     f = _stencils(1 << 20, seed=3)
     g = api.reconstruct(to_dev(f)).cpu().numpy()
     assert np.isfinite(g).all()
+
+
+@pytest.mark.parametrize("weights,scheme", [("zn", 0), ("z", 1)])
+@pytest.mark.parametrize("s", [1e-30, 1e-12, 1e12, 1e20])
+def test_reconstruct_extreme_magnitudes(api, orc, weights, scheme, s):
+    """The single-divide form keeps its products inside the fp64 range for window values up
+    to 1e26 in magnitude (the largest, the numerator term, grows as |f|^11; with eps = 1e-40
+    the smallest is about eps^5).  Stencils scaled by s (the largest value, the scaled 1e6 step,
+    reaches 1e26; at s = 1e-30 eps dominates every indicator), including near-constant ones,
+    against the oracle's literal form."""
+    note("reconstruct extreme magnitudes", weights, s)
+    m = 2001
+    f = _stencils(m, seed=91 + scheme) * s
+    f[:, 5] = s * (1.0 + 1e-9 * np.arange(5) ** 2)  # near-constant at this magnitude
+    g = api.reconstruct(to_dev(f), api.params("euler", weights=weights)).cpu().numpy()
+    prm = orc.params(scheme=scheme, q=1)
+    r = np.array([orc.reconstruct(f[:, i], prm)["fhat"] for i in range(m)])
+    scale = np.abs(f).max(axis=0)
+    assert np.isfinite(g).all()
+    assert np.all(np.abs(g - r) <= 1e-13 * scale), np.max(np.abs(g - r) / scale)
