@@ -29,6 +29,10 @@
  *   - Arguments are validated before anything is enqueued; on error nothing is enqueued and
  *     a status code is returned (wzn_last_error() then describes it).  No C++ exception
  *     crosses the ABI.  A failed launch returns WZN_ERR_HIP.
+ *   - Range: the fp64 weights are evaluated in a single-divide product form whose largest
+ *     term grows as the 11th power of the reconstructed values.  Split fluxes F +- alpha U
+ *     (wzn_reconstruct: point values) up to 1e26 in magnitude are evaluated correctly; beyond
+ *     about 3e27 they overflow to non-finite outputs, reported only by the debug scan.
  */
 #ifndef WENOZN_H
 #define WENOZN_H
