@@ -61,6 +61,8 @@ def lib():
                                          C.POINTER(OrcParams), d, d, p, p]
         L.orc_rk3_step_1d_c128.argtypes = [i32, i32, i64, p, d, d, p, C.POINTER(OrcParams),
                                            d, d]
+        L.orc_rk3_run_1d_c128.argtypes = [i32, i32, i64, p, d, C.c_int32, p, p,
+                                          C.POINTER(OrcParams), d, d]
         L.orc_rhs_2d_f64.argtypes = [i32, i32, i64, i64, p, p, d, d, d, d,
                                      C.POINTER(OrcParams), d, p]
         L.orc_rk3_run_2d_f64.argtypes = [i32, i32, i64, i64, p, d, d, d, C.c_int32, p,
@@ -71,7 +73,7 @@ def lib():
         L.orc_sw_split_f64.argtypes = [p, i32, d, p, p]
         L.orc_rk3_run_2d_sw_f64.argtypes = [i32, i32, i64, i64, p, d, d, d, C.c_int32, p,
                                             C.POINTER(OrcParams), d, p]
-        L.orc_rk3_run_1d_char_f64.argtypes = [i32, i64, p, d, d, C.c_int32,
+        L.orc_rk3_run_1d_char_f64.argtypes = [i32, i64, p, d, d, C.c_int32, p,
                                               C.POINTER(OrcParams), d, p, p]
         L.orc_rhs_2d_char_f64.argtypes = [i32, i32, i64, i64, p, p, d, d, p,
                                           C.POINTER(OrcParams), d, p]
@@ -185,6 +187,21 @@ def rk3_step_1d_complex(u, dx, dt, alpha3, sys=SYS_EULER1, bc=BC_PERIODIC, prm=N
     return u
 
 
+def rk3_run_1d_complex(u, dx, dts, alphas, sys=SYS_EULER1, bc=BC_PERIODIC, prm=None, a=1.0,
+                       gamma=GAMMA):
+    """len(dts) TVD-RK3 steps of a complex state with the frozen schedule dts [nsteps],
+    alphas [nsteps, 3] (complex-step directional derivatives of a whole run)."""
+    prm = prm or params()
+    u = np.ascontiguousarray(u, dtype=np.complex128).copy()
+    n = u.shape[-1]
+    dts = _f64(dts).reshape(-1)
+    al = _f64(alphas).reshape(-1)
+    assert al.size == 3 * dts.size
+    lib().orc_rk3_run_1d_c128(sys, bc, n, _ptr(u), dx, int(dts.size), _ptr(dts), _ptr(al),
+                              C.byref(prm), a, gamma)
+    return u
+
+
 def rhs_2d(u, dx, dy, bcx=BC_TRANSMISSIVE, bcy=BC_TRANSMISSIVE, alpha_x=-1.0, alpha_y=-1.0,
            prm=None, gamma=GAMMA):
     """L(U) for a [4, ny, nx] state; returns (L, (alpha_x, alpha_y))."""
@@ -265,16 +282,20 @@ def roe_eigen(UL, UR, gamma=GAMMA):
     return R.reshape(3, 3), Lc.reshape(3, 3)
 
 
-def rk3_run_1d_char(u, dx, nsteps, cfl=0.5, bc=BC_TRANSMISSIVE, prm=None, gamma=GAMMA):
-    """nsteps TVD-RK3 steps of the characteristic scheme; returns (u, dt[nsteps],
-    alpha[nsteps, 3 stages, 3 fields])."""
+def rk3_run_1d_char(u, dx, nsteps, cfl=0.5, bc=BC_TRANSMISSIVE, prm=None, gamma=GAMMA,
+                    dt=None):
+    """nsteps TVD-RK3 steps of the characteristic scheme (dt: None for the CFL step, or a
+    scalar or [nsteps] of given steps); returns (u, dt[nsteps], alpha[nsteps, 3 stages,
+    3 fields])."""
     prm = prm or params()
     u = _f64(u).copy()
     n = u.shape[-1]
+    if dt is not None:
+        dt = _f64(np.broadcast_to(np.asarray(dt, dtype=np.float64), (nsteps,)))
     dt_out = np.zeros(nsteps)
     al_out = np.zeros(nsteps * 9)
-    lib().orc_rk3_run_1d_char_f64(bc, n, _ptr(u), dx, cfl, nsteps, C.byref(prm), gamma,
-                                  _ptr(dt_out), _ptr(al_out))
+    lib().orc_rk3_run_1d_char_f64(bc, n, _ptr(u), dx, cfl, nsteps, _ptr(dt), C.byref(prm),
+                                  gamma, _ptr(dt_out), _ptr(al_out))
     return u, dt_out, al_out.reshape(nsteps, 3, 3)
 
 

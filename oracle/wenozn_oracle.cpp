@@ -763,6 +763,16 @@ void orc_rk3_step_1d_c128(int sys, int bc, int64_t n, double* u_ri, double dx, d
   }
 }
 
+// ---- nsteps TVD-RK3 steps with complex state and the frozen schedule dts[nsteps],
+// alphas[nsteps][3] (complex-step directional derivatives of a whole run): the step above,
+// applied nsteps times.  u_ri: interleaved (re, im), updated in place.
+void orc_rk3_run_1d_c128(int sys, int bc, int64_t n, double* u_ri, double dx, int32_t nsteps,
+                         const double* dts, const double* alphas, const OrcParams* P, double a,
+                         double gamma) {
+  for (int32_t s = 0; s < nsteps; ++s)
+    orc_rk3_step_1d_c128(sys, bc, n, u_ri, dx, dts[s], alphas + 3 * s, P, a, gamma);
+}
+
 // ---- 2D RHS (fp64).  alpha_x/alpha_y < 0: compute from u.  Returns both alphas.
 void orc_rhs_2d_f64(int bcx, int bcy, int64_t nx, int64_t ny, const double* u, double* dudt,
                     double dx, double dy, double alpha_x, double alpha_y, const OrcParams* P,
@@ -868,18 +878,19 @@ void orc_roe_eigen_f64(const double* UL, const double* UR, double gamma, double*
 }
 
 // ---- nsteps TVD-RK3 steps of the characteristic scheme, in place.  dt from U^n as
-// cfl dx / max(|u| + c) (Sec. 4.3); per-field alphas recomputed for every stage.
-// dt_out [nsteps] and alpha_out [nsteps][3 stages][3 fields] may be NULL.
+// cfl dx / max(|u| + c) (Sec. 4.3) unless dt_in [nsteps] gives it; per-field alphas
+// recomputed for every stage.  dt_out [nsteps] and alpha_out [nsteps][3 stages][3 fields] may
+// be NULL.
 void orc_rk3_run_1d_char_f64(int bc, int64_t n, double* u, double dx, double cfl,
-                             int32_t nsteps, const OrcParams* P, double gamma, double* dt_out,
-                             double* alpha_out) {
+                             int32_t nsteps, const double* dt_in, const OrcParams* P,
+                             double gamma, double* dt_out, double* alpha_out) {
   Phys ph{0.0, gamma};
   const int64_t M = 3 * n;
   std::vector<double> un(M), us(M), L(M);
   for (int32_t st = 0; st < nsteps; ++st) {
     std::memcpy(un.data(), u, sizeof(double) * M);
     std::memcpy(us.data(), u, sizeof(double) * M);
-    const double dt = cfl * dx / lf_alpha_1d(SYS_EULER1, n, u, ph);
+    const double dt = dt_in ? dt_in[st] : cfl * dx / lf_alpha_1d(SYS_EULER1, n, u, ph);
     for (int s = 0; s < 3; ++s) {
       double a3[3];
       lf_alpha_char(n, us.data(), ph, a3);
