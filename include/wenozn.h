@@ -31,8 +31,14 @@
  *     crosses the ABI.  A failed launch returns WZN_ERR_HIP.
  *   - Range: the fp64 weights are evaluated in a single-divide product form whose largest
  *     term grows as the 11th power of the reconstructed values.  Split fluxes F +- alpha U
- *     (wzn_reconstruct: point values) up to 1e26 in magnitude are evaluated correctly; beyond
- *     about 3e27 they overflow to non-finite outputs, reported only by the debug scan.
+ *     (wzn_reconstruct: point values) up to 1e26 in magnitude are evaluated correctly; from
+ *     about 1e27 (an alternating window) they overflow to non-finite outputs.  The debug mode
+ *     (p->debug_nonfinite) reports both the non-finite outputs and states beyond the range
+ *     (in fp32 the squared differences of the window reach FLT_MAX from about 1e18, so the
+ *     debug mode flags fp32 split fluxes beyond 1e17).
+ *     For the same reason eps must lie in [1e-60, 1e50] in fp64 (its fifth power, the
+ *     smallest product on a flat stencil, must stay a normal double), and in [1e-36, 1e30]
+ *     in fp32; other values return WZN_ERR_ARG.
  */
 #ifndef WENOZN_H
 #define WENOZN_H
@@ -54,7 +60,10 @@ enum {
   WZN_ERR_DTYPE = 3,      /* unsupported dtype for this entry point */
   WZN_ERR_HIP = 4,        /* a HIP runtime call or kernel launch failed */
   WZN_ERR_NONFINITE = 5,  /* the output holds NaN or Inf (only with p->debug_nonfinite set) */
-  WZN_ERR_UNSUPPORTED = 6 /* parameter combination not implemented on the GPU */
+  WZN_ERR_UNSUPPORTED = 6, /* parameter combination not implemented on the GPU */
+  WZN_ERR_NONPHYSICAL = 7, /* an Euler state holds rho <= 0 or p <= 0 (debug_nonfinite only) */
+  WZN_ERR_RANGE = 8        /* split fluxes may exceed the range the weights are evaluated for
+                              (debug_nonfinite only; see "Range" above) */
 };
 
 enum { WZN_ADVECTION = 0, WZN_EULER = 1 };          /* system */
@@ -86,11 +95,21 @@ typedef struct {
                            wzn_rhs_1d, wzn_rk3_run_1d, wzn_rk3_step_1d and wzn_reconstruct
                            only (others return WZN_ERR_UNSUPPORTED) */
   int32_t debug_nonfinite; /* 0 (default): nothing is checked and nothing synchronises.
-                           1: a debugging aid -- every entry point with a workspace scans the
-                           array it writes (dudt, the advanced state, the cotangent) after its
-                           work, synchronises `stream`, and returns WZN_ERR_NONFINITE if any
-                           value is NaN or Inf (wzn_last_error() gives their count and one
-                           index).  The scan blocks the host; keep it off in production. */
+                           1: a debugging aid -- after its work every entry point with a
+                           workspace synchronises `stream` and checks
+                           - the array it writes (dudt, the advanced state, the cotangent):
+                             WZN_ERR_NONFINITE if any value is NaN or Inf;
+                           - the state it read (right-hand sides, adjoints: u, the stage states
+                             or checkpoints; checked before the output, which such a state
+                             explains) or wrote (runs; checked after the output):
+                             WZN_ERR_NONPHYSICAL if a cell has rho <= 0 or p <= 0 (Euler) or a
+                             non-finite value, and, except on the characteristic-field paths,
+                             WZN_ERR_RANGE if the bound max|F| + alpha max|U| of its split
+                             fluxes (per component and direction; alpha the frozen value or the
+                             state's largest wave speed) exceeds 1e26 (fp64) or 1e17 (fp32).
+                           wzn_last_error() gives counts and one index.  The work itself has
+                           been done when these are returned.  The scans block the host; keep
+                           the mode off in production. */
 } wzn_params;
 
 /* Fill *p with the paper's values for `system`: A = 10, eps = 1e-40, p_C = 2, q = 1,
@@ -301,9 +320,14 @@ int32_t wzn_rk3_run_2d_char(const wzn_params* p, void* u, void* stage, void* wor
  *   stage    device scratch of 2 * 3 * total doubles.
  *   offsets  device int64 [batch + 1], non-decreasing, offsets[batch] == total; every instance
  *            must have 6 .. 2^30 cells (other or out-of-range instances are skipped unchanged).
+ *            Decreasing offsets make instances overlap, and two workgroups would then race on
+ *            the shared cells; the library does not check this (the Python binding does).
  *   dx       device double [batch].
  *   order    device int32 [batch]: the order in which instances are handed to workgroups
- *            (longest first balances the load), or NULL for 0 .. batch-1.
+ *            (longest first balances the load), or NULL for 0 .. batch-1.  It must be a
+ *            permutation of 0 .. batch-1: an entry outside that range is skipped, and a
+ *            repeated entry makes two workgroups advance the same instance at once (a race;
+ *            not checked on the device, checked by the Python binding).
  *   tuning   host struct (NULL: defaults); nt in {64, 128, 256} threads per workgroup, k in
  *            {1, 2, 4} cells per thread; layout WZN_ROW_LDS_TILE (pairs 64x2, 64x4, 128x2,
  *            128x4, 256x1, 256x2, 256x4) or WZN_ROW_LDS_SPLIT (128x4, 256x2, 256x4), as for

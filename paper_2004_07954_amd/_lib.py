@@ -13,6 +13,8 @@ WZN_ABI_VERSION = 2
 WZN_OK, WZN_ERR_ARG, WZN_ERR_SIZE, WZN_ERR_DTYPE, WZN_ERR_HIP = 0, 1, 2, 3, 4
 WZN_ERR_NONFINITE = 5
 WZN_ERR_UNSUPPORTED = 6
+WZN_ERR_NONPHYSICAL = 7
+WZN_ERR_RANGE = 8
 WZN_ADVECTION, WZN_EULER = 0, 1
 WZN_FP64, WZN_FP32 = 0, 1
 WZN_PERIODIC, WZN_TRANSMISSIVE = 0, 1

@@ -399,6 +399,16 @@ def batched_rk3_run_1d(u, offsets, dx, nsteps, cfl=0.5, prm=None, order=None, tu
     if order is not None and (order.dtype != torch.int32 or not order.is_cuda or
                               order.numel() != batch):
         raise TypeError("order must be a CUDA int32 tensor of batch entries")
+    if not torch.cuda.is_current_stream_capturing():
+        # overlapping instances or a repeated order entry would make two workgroups race on
+        # the same cells; the kernel only skips entries that are out of range.  (Under graph
+        # capture the check, which reads back to the host, is left to the caller.)
+        if batch > 0 and (int(offsets[0]) < 0 or int(offsets[-1]) != total or
+                          bool((offsets[1:] < offsets[:-1]).any())):
+            raise ValueError("offsets must be non-decreasing from >= 0 to u.shape[1]")
+        if order is not None and not torch.equal(
+                torch.sort(order.long())[0], torch.arange(batch, device=order.device)):
+            raise ValueError("order must be a permutation of 0 .. batch-1")
     if stage is None:
         stage = torch.empty((2, 3, total), dtype=torch.float64, device=u.device)
     if stage.numel() < 2 * u.numel() or not stage.is_contiguous():

@@ -220,6 +220,152 @@ int debug_nonfinite_scan(const void* x, int64_t count, bool f32, Workspace* ws, 
   return WZN_OK;
 }
 
+// The debug mode's scan of a state (the input of a right-hand side, or the result of a run):
+// the count of cells with rho <= 0 or p <= 0 (or not finite) and the largest index + 1 of one,
+// and, over the other cells, the maxima from which the host bounds the split fluxes the
+// reconstruction sees.  Words of out (zero beforehand; maxima as bit patterns of non-negative
+// doubles): [0] count, [1] last index + 1, [2 + c] max |F_c|, [6 + c] max |G_c| (2D),
+// [10 + c] max |U_c|, [14] max |u| + c, [15] max |v| + c.
+constexpr int STATE_SCAN_WORDS = 16;
+
+template <int NV, typename T>
+__global__ __launch_bounds__(256) void state_scan_kernel(const T* __restrict__ u, int64_t N,
+                                                         double gamma, double adv,
+                                                         unsigned long long* out) {
+  unsigned long long bad = 0, last = 0;
+  double mF[4] = {0.0, 0.0, 0.0, 0.0}, mG[4] = {0.0, 0.0, 0.0, 0.0};
+  double mU[4] = {0.0, 0.0, 0.0, 0.0}, sx = 0.0, sy = 0.0;
+  const double gm1 = gamma - 1.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * 256) {
+    double U[4] = {0.0, 0.0, 0.0, 0.0}, F[4] = {0.0, 0.0, 0.0, 0.0}, G[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int c = 0; c < NV; ++c) U[c] = double(u[c * N + i]);
+    bool ok;
+    if constexpr (NV == 1) {
+      F[0] = adv * U[0];
+      ok = __builtin_isfinite(U[0]);
+    } else if constexpr (NV == 3) {
+      const double v = U[1] / U[0];
+      const double p = gm1 * (U[2] - 0.5 * U[1] * v);
+      F[0] = U[1];
+      F[1] = U[1] * v + p;
+      F[2] = v * (U[2] + p);
+      ok = U[0] > 0.0 && p > 0.0 && __builtin_isfinite(U[0] + U[1] + U[2]);
+      if (ok) sx = fmax(sx, __builtin_fabs(v) + sqrt(gamma * p / U[0]));
+    } else {
+      const double vx = U[1] / U[0], vy = U[2] / U[0];
+      const double p = gm1 * (U[3] - 0.5 * (U[1] * vx + U[2] * vy));
+      F[0] = U[1];
+      F[1] = U[1] * vx + p;
+      F[2] = U[2] * vx;
+      F[3] = vx * (U[3] + p);
+      G[0] = U[2];
+      G[1] = U[1] * vy;
+      G[2] = U[2] * vy + p;
+      G[3] = vy * (U[3] + p);
+      ok = U[0] > 0.0 && p > 0.0 && __builtin_isfinite(U[0] + U[1] + U[2] + U[3]);
+      if (ok) {
+        const double c = sqrt(gamma * p / U[0]);
+        sx = fmax(sx, __builtin_fabs(vx) + c);
+        sy = fmax(sy, __builtin_fabs(vy) + c);
+      }
+    }
+    if (!ok) {
+      ++bad;
+      last = (unsigned long long)i + 1;
+      continue;
+    }
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+      mF[c] = fmax(mF[c], __builtin_fabs(F[c]));
+      mG[c] = fmax(mG[c], __builtin_fabs(G[c]));
+      mU[c] = fmax(mU[c], __builtin_fabs(U[c]));
+    }
+  }
+  if (bad) {
+    atomicAdd(&out[0], bad);
+    atomicMax(&out[1], last);
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    mF[c] = wave_max(mF[c]);
+    mG[c] = wave_max(mG[c]);
+    mU[c] = wave_max(mU[c]);
+  }
+  sx = wave_max(sx);
+  sy = wave_max(sy);
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+      atomic_max_pos(&out[2 + c], mF[c]);
+      atomic_max_pos(&out[6 + c], mG[c]);
+      atomic_max_pos(&out[10 + c], mU[c]);
+    }
+    atomic_max_pos(&out[14], sx);
+    atomic_max_pos(&out[15], sy);
+  }
+}
+
+int debug_state_scan(const wzn_params* p, const void* u, int64_t N, int nv, bool f32,
+                     bool check_range, Workspace* ws, hipStream_t s) {
+  if (!p->debug_nonfinite) return WZN_OK;
+  unsigned long long* w = ws->scratch + 8;
+  int st = launch_zero_words(w, STATE_SCAN_WORDS, s);
+  if (st) return st;
+  int64_t blocks = (N + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  const dim3 g((unsigned)blocks), b(256);
+  if (nv == 1) {
+    hipLaunchKernelGGL((state_scan_kernel<1, double>), g, b, 0, s, (const double*)u, N,
+                       p->gamma, p->adv_speed, w);
+  } else if (nv == 3) {
+    hipLaunchKernelGGL((state_scan_kernel<3, double>), g, b, 0, s, (const double*)u, N,
+                       p->gamma, 0.0, w);
+  } else if (f32) {
+    hipLaunchKernelGGL((state_scan_kernel<4, float>), g, b, 0, s, (const float*)u, N, p->gamma,
+                       0.0, w);
+  } else {
+    hipLaunchKernelGGL((state_scan_kernel<4, double>), g, b, 0, s, (const double*)u, N,
+                       p->gamma, 0.0, w);
+  }
+  st = check_launch("state_scan_kernel");
+  if (st) return st;
+  unsigned long long h[STATE_SCAN_WORDS];
+  if (hipMemcpyAsync(h, w, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return set_error(WZN_ERR_HIP, "debug scan: copy of the state scan failed");
+  if (h[0])
+    return set_error(WZN_ERR_NONPHYSICAL,
+                     "%llu cells with rho <= 0 or p <= 0 or a non-finite value (one at cell %lld)",
+                     h[0], (long long)h[1] - 1);
+  if (!check_range) return WZN_OK;
+  double v[STATE_SCAN_WORDS];
+  for (int k = 2; k < STATE_SCAN_WORDS; ++k) v[k] = __builtin_bit_cast(double, h[k]);
+  // |F +- alpha U| <= |F| + alpha |U|: the Lax-Friedrichs alpha is the frozen one or the
+  // state's largest wave speed, which also bounds the Steger-Warming split (its
+  // eigenvalues are at most |u| + c)
+  const bool adv = nv == 1;
+  double ax = p->lf_alpha_x >= 0.0 ? p->lf_alpha_x : (adv ? __builtin_fabs(p->adv_speed) : v[14]);
+  double ay = p->lf_alpha_y >= 0.0 ? p->lf_alpha_y : v[15];
+  if (nv == 4 && p->flux_split == WZN_SPLIT_SW) {
+    ax = v[14];
+    ay = v[15];
+  }
+  double bound = 0.0;
+  for (int c = 0; c < nv; ++c) {
+    bound = fmax(bound, v[2 + c] + ax * v[10 + c]);
+    if (nv == 4) bound = fmax(bound, v[6 + c] + ay * v[10 + c]);
+  }
+  const double limit = f32 ? 1e17 : 1e26;
+  if (!(bound <= limit))
+    return set_error(WZN_ERR_RANGE,
+                     "split fluxes may reach %.3g, beyond the %.0e the weights are evaluated for",
+                     bound, limit);
+  return WZN_OK;
+}
+
 static const double RK_A[3] = {0.0, 3.0 / 4.0, 1.0 / 3.0};
 static const double RK_B[3] = {1.0, 1.0 / 4.0, 2.0 / 3.0};
 

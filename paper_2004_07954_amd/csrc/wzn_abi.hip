@@ -77,6 +77,12 @@ static int check_params(const wzn_params* p, bool allow_fp32, bool allow_z = fal
                      "the WENO-Z weights run in wzn_rhs_1d, wzn_rk3_run_1d and wzn_reconstruct");
   if (!(p->eps > 0.0) || !(p->A > 0.0))
     return set_error(WZN_ERR_ARG, "eps and A must be positive");
+  // the fp64 product form multiplies five eps-sized factors on a flat stencil (the smallest
+  // product, which must stay a normal double) and the fp32 form needs 16 eps normal
+  if (p->dtype == WZN_FP64 && !(p->eps >= 1e-60 && p->eps <= 1e50))
+    return set_error(WZN_ERR_ARG, "fp64 needs 1e-60 <= eps <= 1e50 (got %g)", p->eps);
+  if (p->dtype == WZN_FP32 && !(p->eps >= 1e-36 && p->eps <= 1e30))
+    return set_error(WZN_ERR_ARG, "fp32 needs 1e-36 <= eps <= 1e30 (got %g)", p->eps);
   if (p->system == WZN_EULER && !(p->gamma > 1.0))
     return set_error(WZN_ERR_ARG, "gamma must exceed 1");
   if (p->system == WZN_ADVECTION && !(p->adv_speed != 0.0) && p->lf_alpha_x < 0.0)
@@ -89,6 +95,16 @@ static int scanned(int st, const wzn_params* p, const void* x, int64_t count, bo
                    Workspace* w, void* stream) {
   if (st || !p->debug_nonfinite) return st;
   return debug_nonfinite_scan(x, count, f32, w, (hipStream_t)stream);
+}
+
+// The debug mode's check of a state after an entry point's work: the state it read (right-hand
+// sides, adjoints) or wrote (runs) has rho, p > 0 and split fluxes inside the weights' range
+// (the range is not checked for the characteristic-field paths, whose reconstructed values are
+// projections of the split fluxes).
+static int state_checked(int st, const wzn_params* p, const void* state, int64_t N, int nv,
+                         bool f32, bool range, Workspace* w, void* stream) {
+  if (st || !p->debug_nonfinite) return st;
+  return debug_state_scan(p, state, N, nv, f32, range, w, (hipStream_t)stream);
 }
 
 static int check_1d(const wzn_params* p, int64_t n, double dx, void* ws, bool allow_z = false) {
@@ -115,8 +131,6 @@ static int check_2d(const wzn_params* p, int64_t nx, int64_t ny, double dx, doub
   if (nx > (1 << 24) || ny > (1 << 24) || nx * ny > ((int64_t)1 << 36))
     return set_error(WZN_ERR_SIZE, "grid %lld x %lld too large", (long long)nx, (long long)ny);
   if (!(dx > 0.0) || !(dy > 0.0)) return set_error(WZN_ERR_ARG, "dx and dy must be positive");
-  if (p->dtype == WZN_FP32 && !(p->eps >= 1e-36))
-    return set_error(WZN_ERR_ARG, "fp32 needs eps >= 1e-36 (16 eps must be a normal float)");
   if (!ws) return set_error(WZN_ERR_ARG, "workspace is NULL");
   if (((uintptr_t)ws) & 255) return set_error(WZN_ERR_ARG, "workspace not 256-byte aligned");
   return WZN_OK;
@@ -156,6 +170,8 @@ const char* wzn_status_string(int32_t status) {
     case WZN_ERR_HIP: return "HIP error";
     case WZN_ERR_NONFINITE: return "non-finite output";
     case WZN_ERR_UNSUPPORTED: return "unsupported parameters";
+    case WZN_ERR_NONPHYSICAL: return "non-physical state";
+    case WZN_ERR_RANGE: return "values beyond the evaluated range";
     default: return "unknown status";
   }
 }
@@ -219,8 +235,9 @@ int32_t wzn_rhs_1d(const wzn_params* p, const void* u, void* dudt, int64_t n, do
   if (u == dudt) return set_error(WZN_ERR_ARG, "u and dudt must not alias");
   Workspace w = make_workspace(ws);
   const int64_t nv = p->system == WZN_EULER ? 3 : 1;
-  return scanned(rhs_1d(p, (const double*)u, (double*)dudt, n, dx, &w, (hipStream_t)stream), p,
-                 dudt, nv * n, false, &w, stream);
+  st = state_checked(rhs_1d(p, (const double*)u, (double*)dudt, n, dx, &w, (hipStream_t)stream),
+                     p, u, n, (int)nv, false, true, &w, stream);
+  return scanned(st, p, dudt, nv * n, false, &w, stream);
 }
 
 int32_t wzn_speed_max_1d(const wzn_params* p, const void* u, int64_t n, double* speed1,
@@ -231,7 +248,8 @@ int32_t wzn_speed_max_1d(const wzn_params* p, const void* u, int64_t n, double* 
   if (p->system != WZN_EULER) return set_error(WZN_ERR_ARG, "1D Euler only");
   if (!u || !speed1) return set_error(WZN_ERR_ARG, "NULL array argument");
   Workspace w = make_workspace(ws);
-  return speed_max_1d(p, (const double*)u, n, speed1, &w, (hipStream_t)stream);
+  st = speed_max_1d(p, (const double*)u, n, speed1, &w, (hipStream_t)stream);
+  return state_checked(st, p, u, n, 3, false, false, &w, stream);
 }
 
 int32_t wzn_rhs_1d_slab(const wzn_params* p, const void* u, const void* ghost_lo,
@@ -245,10 +263,11 @@ int32_t wzn_rhs_1d_slab(const wzn_params* p, const void* u, const void* ghost_lo
     return set_error(WZN_ERR_ARG, "NULL argument");
   if (u == dudt) return set_error(WZN_ERR_ARG, "u and dudt must not alias");
   Workspace w = make_workspace(ws);
-  return scanned(rhs_1d_slab(p, (const double*)u, (const double*)ghost_lo,
-                             (const double*)ghost_hi, (double*)dudt, n, dx, alpha,
-                             (hipStream_t)stream),
-                 p, dudt, 3 * n, false, &w, stream);
+  st = state_checked(rhs_1d_slab(p, (const double*)u, (const double*)ghost_lo,
+                                 (const double*)ghost_hi, (double*)dudt, n, dx, alpha,
+                                 (hipStream_t)stream),
+                     p, u, n, 3, false, true, &w, stream);
+  return scanned(st, p, dudt, 3 * n, false, &w, stream);
 }
 
 int32_t wzn_rk3_run_1d(const wzn_params* p, void* u, void* stage, int64_t n, double dx,
@@ -262,9 +281,10 @@ int32_t wzn_rk3_run_1d(const wzn_params* p, void* u, void* stage, int64_t n, dou
   if (!dt_in && !(cfl > 0.0)) return set_error(WZN_ERR_ARG, "cfl must be positive");
   Workspace w = make_workspace(ws);
   const int64_t nv = p->system == WZN_EULER ? 3 : 1;
-  return scanned(rk3_run_1d(p, (double*)u, (double*)stage, n, dx, cfl, nsteps, dt_in, alpha_in,
-                            dt_out, alpha_out, &w, (hipStream_t)stream),
-                 p, u, nv * n, false, &w, stream);
+  st = scanned(rk3_run_1d(p, (double*)u, (double*)stage, n, dx, cfl, nsteps, dt_in, alpha_in,
+                          dt_out, alpha_out, &w, (hipStream_t)stream),
+               p, u, nv * n, false, &w, stream);
+  return state_checked(st, p, u, n, (int)nv, false, true, &w, stream);
 }
 
 int32_t wzn_rk3_step_1d(const wzn_params* p, void* u, void* stage, int64_t n, double dx,
@@ -283,9 +303,10 @@ int32_t wzn_rhs_1d_char(const wzn_params* p, const void* u, void* dudt, int64_t 
   if (!u || !dudt) return set_error(WZN_ERR_ARG, "u or dudt is NULL");
   if (u == dudt) return set_error(WZN_ERR_ARG, "u and dudt must not alias");
   Workspace w = make_workspace(ws);
-  return scanned(rhs_1d_char(p, (const double*)u, (double*)dudt, n, dx, alpha3, &w,
-                             (hipStream_t)stream),
-                 p, dudt, 3 * n, false, &w, stream);
+  st = state_checked(rhs_1d_char(p, (const double*)u, (double*)dudt, n, dx, alpha3, &w,
+                                 (hipStream_t)stream),
+                     p, u, n, 3, false, false, &w, stream);
+  return scanned(st, p, dudt, 3 * n, false, &w, stream);
 }
 
 int32_t wzn_rk3_run_1d_char(const wzn_params* p, void* u, void* stage, int64_t n, double dx,
@@ -301,9 +322,10 @@ int32_t wzn_rk3_run_1d_char(const wzn_params* p, void* u, void* stage, int64_t n
   if (nsteps < 0) return set_error(WZN_ERR_ARG, "nsteps < 0");
   if (!dt_in && !(cfl > 0.0)) return set_error(WZN_ERR_ARG, "cfl must be positive");
   Workspace w = make_workspace(ws);
-  return scanned(rk3_run_1d_char(p, (double*)u, (double*)stage, n, dx, cfl, nsteps, dt_in,
-                                 alpha_in, dt_out, alpha_out, &w, (hipStream_t)stream),
-                 p, u, 3 * n, false, &w, stream);
+  st = scanned(rk3_run_1d_char(p, (double*)u, (double*)stage, n, dx, cfl, nsteps, dt_in,
+                               alpha_in, dt_out, alpha_out, &w, (hipStream_t)stream),
+               p, u, 3 * n, false, &w, stream);
+  return state_checked(st, p, u, n, 3, false, false, &w, stream);
 }
 
 int32_t wzn_rhs_2d(const wzn_params* p, const void* u, void* dudt, int64_t nx, int64_t ny,
@@ -319,6 +341,7 @@ int32_t wzn_rhs_2d(const wzn_params* p, const void* u, void* dudt, int64_t nx, i
                              (hipStream_t)stream)
            : rhs_2d_t<double>(p, (const double*)u, (double*)dudt, nx, ny, dx, dy, &w,
                               (hipStream_t)stream);
+  st = state_checked(st, p, u, nx * ny, 4, f32, true, &w, stream);
   return scanned(st, p, dudt, 4 * nx * ny, f32, &w, stream);
 }
 
@@ -341,6 +364,7 @@ int32_t wzn_rhs_2d_strip(const wzn_params* p, const void* u, const void* ghost_l
            : rhs_2d_strip_t<double>(p, (const double*)u, (const double*)ghost_lo,
                                     (const double*)ghost_hi, (double*)dudt, nx, ny, dx, dy,
                                     alpha2, (hipStream_t)stream);
+  st = state_checked(st, p, u, nx * ny, 4, f32, true, &w, stream);
   return scanned(st, p, dudt, 4 * nx * ny, f32, &w, stream);
 }
 
@@ -351,9 +375,11 @@ int32_t wzn_speed_max_2d(const wzn_params* p, const void* u, int64_t nx, int64_t
   if (st) return st;
   if (!u || !speed2) return set_error(WZN_ERR_ARG, "NULL array argument");
   Workspace w = make_workspace(ws);
-  if (p->dtype == WZN_FP32)
-    return speed_max_2d_t<float>(p, (const float*)u, nx, ny, speed2, &w, (hipStream_t)stream);
-  return speed_max_2d_t<double>(p, (const double*)u, nx, ny, speed2, &w, (hipStream_t)stream);
+  const bool f32 = p->dtype == WZN_FP32;
+  st = f32 ? speed_max_2d_t<float>(p, (const float*)u, nx, ny, speed2, &w, (hipStream_t)stream)
+           : speed_max_2d_t<double>(p, (const double*)u, nx, ny, speed2, &w,
+                                    (hipStream_t)stream);
+  return state_checked(st, p, u, nx * ny, 4, f32, false, &w, stream);
 }
 
 int32_t wzn_rk3_run_2d(const wzn_params* p, void* u, void* stage, int64_t nx, int64_t ny,
@@ -371,7 +397,8 @@ int32_t wzn_rk3_run_2d(const wzn_params* p, void* u, void* stage, int64_t nx, in
                                  dt_in, dt_out, &w, (hipStream_t)stream)
            : rk3_run_2d_t<double>(p, (double*)u, (double*)stage, nx, ny, dx, dy, cfl, nsteps,
                                   dt_in, dt_out, &w, (hipStream_t)stream);
-  return scanned(st, p, u, 4 * nx * ny, f32, &w, stream);
+  st = scanned(st, p, u, 4 * nx * ny, f32, &w, stream);
+  return state_checked(st, p, u, nx * ny, 4, f32, true, &w, stream);
 }
 
 int64_t wzn_char2d_work_doubles(int64_t nx, int64_t ny) {
@@ -402,9 +429,10 @@ int32_t wzn_rhs_2d_char(const wzn_params* p, const void* u, void* dudt, void* wo
   if (u == dudt || work == u || work == dudt)
     return set_error(WZN_ERR_ARG, "u, dudt and work must not alias");
   Workspace w = make_workspace(ws);
-  return scanned(rhs_2d_char(p, (const double*)u, (double*)dudt, (double*)work, nx, ny, dx, dy,
-                             alpha8, &w, (hipStream_t)stream),
-                 p, dudt, 4 * nx * ny, false, &w, stream);
+  st = state_checked(rhs_2d_char(p, (const double*)u, (double*)dudt, (double*)work, nx, ny, dx,
+                                 dy, alpha8, &w, (hipStream_t)stream),
+                     p, u, nx * ny, 4, false, false, &w, stream);
+  return scanned(st, p, dudt, 4 * nx * ny, false, &w, stream);
 }
 
 int32_t wzn_rk3_run_2d_char(const wzn_params* p, void* u, void* stage, void* work, int64_t nx,
@@ -419,9 +447,10 @@ int32_t wzn_rk3_run_2d_char(const wzn_params* p, void* u, void* stage, void* wor
   if (nsteps < 0) return set_error(WZN_ERR_ARG, "nsteps < 0");
   if (!dt_in && !(cfl > 0.0)) return set_error(WZN_ERR_ARG, "cfl must be positive");
   Workspace w = make_workspace(ws);
-  return scanned(rk3_run_2d_char(p, (double*)u, (double*)stage, (double*)work, nx, ny, dx, dy,
-                                 cfl, nsteps, dt_in, dt_out, &w, (hipStream_t)stream),
-                 p, u, 4 * nx * ny, false, &w, stream);
+  st = scanned(rk3_run_2d_char(p, (double*)u, (double*)stage, (double*)work, nx, ny, dx, dy,
+                               cfl, nsteps, dt_in, dt_out, &w, (hipStream_t)stream),
+               p, u, 4 * nx * ny, false, &w, stream);
+  return state_checked(st, p, u, nx * ny, 4, false, false, &w, stream);
 }
 
 int32_t wzn_rk3_step_2d(const wzn_params* p, void* u, void* stage, int64_t nx, int64_t ny,
@@ -452,9 +481,10 @@ int32_t wzn_batched_rk3_run_1d(const wzn_params* p, void* u, void* stage, int64_
     if (!ok) return set_error(WZN_ERR_ARG, "unsupported batched tuning (nt=%d, k=%d)", nt, k);
   }
   Workspace w = make_workspace(ws);
-  return scanned(batched_rk3_run_1d(p, (double*)u, (double*)stage, total, offsets, dx, order,
-                                    batch, nsteps, cfl, tuning, dt_out, &w, (hipStream_t)stream),
-                 p, u, 3 * total, false, &w, stream);
+  st = scanned(batched_rk3_run_1d(p, (double*)u, (double*)stage, total, offsets, dx, order,
+                                  batch, nsteps, cfl, tuning, dt_out, &w, (hipStream_t)stream),
+               p, u, 3 * total, false, &w, stream);
+  return state_checked(st, p, u, total, 3, false, true, &w, stream);
 }
 
 int32_t wzn_rhs_1d_vjp(const wzn_params* p, const void* u, const void* mu, void* out, int64_t n,
@@ -466,9 +496,10 @@ int32_t wzn_rhs_1d_vjp(const wzn_params* p, const void* u, const void* mu, void*
   if (!u || !mu || !out) return set_error(WZN_ERR_ARG, "NULL array argument");
   if (out == u || out == mu) return set_error(WZN_ERR_ARG, "out must not alias u or mu");
   Workspace w = make_workspace(ws);
-  return scanned(rhs_1d_vjp(p, (const double*)u, (const double*)mu, (double*)out, n, dx, &w,
-                            (hipStream_t)stream),
-                 p, out, 3 * n, false, &w, stream);
+  st = state_checked(rhs_1d_vjp(p, (const double*)u, (const double*)mu, (double*)out, n, dx, &w,
+                                (hipStream_t)stream),
+                     p, u, n, 3, false, true, &w, stream);
+  return scanned(st, p, out, 3 * n, false, &w, stream);
 }
 
 int32_t wzn_rk3_step_1d_vjp(const wzn_params* p, const void* stages, const void* lam_next,
@@ -483,9 +514,12 @@ int32_t wzn_rk3_step_1d_vjp(const wzn_params* p, const void* stages, const void*
   if (lam_prev == lam_next || lam_prev == stages || lam_prev == scratch)
     return set_error(WZN_ERR_ARG, "lam_prev must not alias the other arrays");
   Workspace w = make_workspace(ws);
-  return scanned(rk3_step_1d_vjp(p, (const double*)stages, (const double*)lam_next, (double*)lam_prev,
-                         (double*)scratch, n, dx, dt, alpha3, &w, (hipStream_t)stream),
-                 p, lam_prev, 3 * n, false, &w, stream);
+  st = rk3_step_1d_vjp(p, (const double*)stages, (const double*)lam_next, (double*)lam_prev,
+                       (double*)scratch, n, dx, dt, alpha3, &w, (hipStream_t)stream);
+  for (int k = 0; k < 3; ++k)
+    st = state_checked(st, p, (const double*)stages + (int64_t)k * 3 * n, n, 3, false, true, &w,
+                       stream);
+  return scanned(st, p, lam_prev, 3 * n, false, &w, stream);
 }
 
 int64_t wzn_rk3_adjoint_1d_work_doubles(int64_t n, int32_t ckpt_every) {
@@ -503,9 +537,13 @@ int32_t wzn_rk3_adjoint_1d(const wzn_params* p, const void* ckpts, int32_t nstep
   if (!ckpts || !dts || !alphas || !lam || !work) return set_error(WZN_ERR_ARG, "NULL argument");
   if (nsteps < 0 || ckpt_every < 1) return set_error(WZN_ERR_ARG, "bad nsteps / ckpt_every");
   Workspace w = make_workspace(ws);
-  return scanned(rk3_adjoint_1d(p, (const double*)ckpts, nsteps, ckpt_every, dts, alphas, (double*)lam,
-                        (double*)work, n, dx, &w, (hipStream_t)stream),
-                 p, lam, 3 * n, false, &w, stream);
+  st = rk3_adjoint_1d(p, (const double*)ckpts, nsteps, ckpt_every, dts, alphas, (double*)lam,
+                      (double*)work, n, dx, &w, (hipStream_t)stream);
+  const int32_t nseg = (nsteps + ckpt_every - 1) / ckpt_every;
+  for (int32_t k = 0; k < nseg; ++k)
+    st = state_checked(st, p, (const double*)ckpts + (int64_t)k * 3 * n, n, 3, false, true, &w,
+                       stream);
+  return scanned(st, p, lam, 3 * n, false, &w, stream);
 }
 
 }  // extern "C"

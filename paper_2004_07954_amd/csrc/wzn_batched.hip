@@ -50,6 +50,7 @@ __global__ __launch_bounds__(NT) void batched_kernel(BatchArgs b) {
     __syncthreads();  // every thread has read `next` before it is overwritten
     if (qi >= b.batch) break;
     const int inst = b.order ? b.order[qi] : qi;
+    if (inst < 0 || inst >= b.batch) continue;  // an order entry out of range: skipped
     const int64_t off = b.offsets[inst];
     const int64_t n = b.offsets[inst + 1] - off;
     // malformed instance (or one longer than a row may be): left untouched

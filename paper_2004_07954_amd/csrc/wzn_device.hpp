@@ -31,8 +31,9 @@
 // B_k times 1/4 (A/4 multiplies num^2 and the fourth difference is not doubled): common
 // factors of numerator and denominator that change no weight.
 // Every product is >= eps^5 ~ 1e-200 for eps = 1e-40.  The largest, the numerator term
-// B2 e_{m+1}, grows as |w|^11: worst-case windows (a step, an alternating sequence) stay finite
-// up to |w| ~ 3e27, so window values are limited to |w| <= 1e26 (split fluxes of that size).
+// B2 e_{m+1}, grows as |w|^11: the worst window, an alternating sequence (-w, w, -w, w, -w),
+// overflows from |w| ~ 1.1e27 (a step from ~5e27), so window values are limited to
+// |w| <= 1e26 (split fluxes of that size).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>

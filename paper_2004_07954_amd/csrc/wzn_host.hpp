@@ -105,6 +105,12 @@ int speed_max_1d(const wzn_params* p, const double* u, int64_t n, double* out, W
 // NaN / Inf scan of an output (the debug_nonfinite mode): synchronises s; WZN_ERR_NONFINITE
 // if any value of x[0 .. count) is not finite
 int debug_nonfinite_scan(const void* x, int64_t count, bool f32, Workspace* ws, hipStream_t s);
+// The debug mode's scan of a state u of N cells and nv components (1: advection, 3: 1D Euler,
+// 4: 2D Euler): WZN_ERR_NONPHYSICAL if a cell has rho <= 0 or p <= 0, and (check_range)
+// WZN_ERR_RANGE if the split fluxes F +- alpha U may exceed the weights' range (1e26 in fp64,
+// 1e17 in fp32).  Does nothing unless p->debug_nonfinite; synchronises s.
+int debug_state_scan(const wzn_params* p, const void* u, int64_t N, int nv, bool f32,
+                     bool check_range, Workspace* ws, hipStream_t s);
 int rk3_run_1d(const wzn_params* p, double* u, double* stage, int64_t n, double dx, double cfl,
                int32_t nsteps, const double* dt_in, const double* alpha_in, double* dt_out,
                double* alpha_out, Workspace* ws, hipStream_t s);

@@ -63,6 +63,36 @@ def test_host_only_calls():
     p.debug_nonfinite = 0
 
 
+@pytest.mark.parametrize("dtype,eps,ok", [
+    (0, 1e-60, True), (0, 1e50, True), (0, 1e-40, True),
+    (0, 1e-61, False), (0, 1e-64, False), (0, 1e51, False), (0, 0.0, False),
+    (0, float("nan"), False), (0, float("inf"), False),
+    (1, 1e-36, True), (1, 1e-30, True), (1, 1e30, True),
+    (1, 1e-37, False), (1, 1e-40, False), (1, 1e31, False)])
+def test_eps_range_rejected_before_launch(dtype, eps, ok):
+    """The weights' product form needs (16 eps)^5 to stay a normal double in fp64 (and 16 eps
+    a normal float in fp32): eps outside [1e-60, 1e50] (fp64) or [1e-36, 1e30] (fp32) is
+    rejected with WZN_ERR_ARG before anything is enqueued.  An accepted eps fails later, on the
+    grid size (n = 5), so no call here launches a kernel."""
+    import ctypes as C
+    from paper_2004_07954_amd import _lib
+    L = _lib.lib()
+    p = _lib.WznParams()
+    L.wzn_default_params(C.byref(p), _lib.WZN_EULER)
+    p.eps = eps
+    p.dtype = dtype
+    if dtype == _lib.WZN_FP64:
+        rc = L.wzn_rhs_1d(C.byref(p), C.c_void_p(256), C.c_void_p(512), 5, 0.1,
+                          C.c_void_p(1024), None)
+    else:
+        rc = L.wzn_rhs_2d(C.byref(p), C.c_void_p(256), C.c_void_p(512), 5, 5, 0.1, 0.1,
+                          C.c_void_p(1024), None)
+    if ok:
+        assert rc == _lib.WZN_ERR_SIZE, L.wzn_last_error()
+    else:
+        assert rc == _lib.WZN_ERR_ARG and b"eps" in L.wzn_last_error(), L.wzn_last_error()
+
+
 def test_row_tuning_host_calls():
     """Launch-shape override: valid shapes are accepted and reported back, unknown ones are
     rejected, (0, 0) restores the size-based choice; over-long rows are rejected."""

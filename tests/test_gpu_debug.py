@@ -1,5 +1,7 @@
 """The debug_nonfinite mode: with it set, an entry point scans its output, synchronises and
-returns WZN_ERR_NONFINITE for NaN / Inf; without it nothing is checked."""
+returns WZN_ERR_NONFINITE for NaN / Inf, then checks the state it read or wrote for rho <= 0
+or p <= 0 (WZN_ERR_NONPHYSICAL) and for split fluxes beyond the weights' range
+(WZN_ERR_RANGE); without it nothing is checked."""
 import numpy as np
 import pytest
 
@@ -30,7 +32,8 @@ def test_nonfinite_reported_only_in_debug_mode(api):
     assert not np.isfinite(L).all()
     with pytest.raises(_lib.WznError) as e:
         api.rhs_1d(to_dev(u), 0.01, api.params("euler", debug_nonfinite=True))
-    assert e.value.code == _lib.WZN_ERR_NONFINITE and "non-finite" in str(e.value)
+    # the input state is checked first: its NaN cell explains the non-finite output
+    assert e.value.code == _lib.WZN_ERR_NONPHYSICAL and "cell 17" in str(e.value)
     good = to_dev(I.random_smooth_1d(500, seed=3))
     api.rhs_1d(good, 0.01, api.params("euler", debug_nonfinite=True))
     api.rk3_run_1d(good, 0.01, 3, prm=api.params("euler", debug_nonfinite=True))
@@ -47,9 +50,74 @@ def test_nonfinite_2d_fp32_and_runs(api):
     bad[3, 10, 20] = np.inf
     with pytest.raises(_lib.WznError) as e:
         api.rhs_2d(to_dev(bad, torch.float32), dx, dy, prm)
-    assert e.value.code == _lib.WZN_ERR_NONFINITE
+    assert e.value.code == _lib.WZN_ERR_NONPHYSICAL and "cell %d" % (10 * 64 + 20) in \
+        str(e.value)
     # a run whose step is far beyond the CFL limit blows up: the scan reports it
     u = to_dev(I.shu_osher_like(400)[0])
     with pytest.raises(_lib.WznError) as e:
         api.rk3_run_1d(u, 0.025, 50, dt=5.0, prm=api.params("euler", debug_nonfinite=True))
     assert e.value.code == _lib.WZN_ERR_NONFINITE
+
+
+def _cons(rho, u, p):
+    return I.prim_to_cons_1d(rho, u, p)
+
+
+def test_nonphysical_state_flagged(api):
+    """A cell with p < 0 (planted from the host) in the input of a right-hand side, of an
+    adjoint and of the 2D path: reported with its index in debug mode only."""
+    import torch
+    from paper_2004_07954_amd import _lib
+    print("[gpu-case] debug nonphysical", flush=True)
+    u = I.random_smooth_1d(600, seed=5)
+    u[2, 123] = 0.4 * u[1, 123] ** 2 / u[0, 123]  # E < m^2 / (2 rho): p < 0 in cell 123
+    ud = to_dev(u)
+    api.rhs_1d(ud, 0.01, api.params("euler", lf_alpha=3.0))  # no scan
+    dbg = api.params("euler", lf_alpha=3.0, debug_nonfinite=True)
+    with pytest.raises(_lib.WznError) as e:
+        api.rhs_1d(ud, 0.01, dbg)
+    assert e.value.code == _lib.WZN_ERR_NONPHYSICAL and "cell 123" in str(e.value)
+    with pytest.raises(_lib.WznError) as e:
+        api.rhs_1d_vjp(ud, torch.ones_like(ud), 0.01, dbg)
+    assert e.value.code == _lib.WZN_ERR_NONPHYSICAL
+    v = I.random_smooth_1d(600, seed=5)
+    v[0, 321] = -1.0  # rho < 0
+    with pytest.raises(_lib.WznError) as e:
+        api.speed_max_1d(to_dev(v), api.params("euler", debug_nonfinite=True))
+    assert e.value.code == _lib.WZN_ERR_NONPHYSICAL and "cell 321" in str(e.value)
+    U, dx, dy = I.riemann_2d(1, 64)
+    U[3, 10, 20] = 0.5 * (U[1, 10, 20] ** 2 + U[2, 10, 20] ** 2) / U[0, 10, 20] * 0.9
+    for dt in (torch.float64, torch.float32):
+        prm = api.params("euler", dtype="fp64" if dt == torch.float64 else "fp32",
+                         eps=1e-40 if dt == torch.float64 else 1e-30, debug_nonfinite=True)
+        with pytest.raises(_lib.WznError) as e:
+            api.rhs_2d(to_dev(U, dt), dx, dy, prm)
+        assert e.value.code == _lib.WZN_ERR_NONPHYSICAL and "cell %d" % (10 * 64 + 20) in \
+            str(e.value)
+
+
+def test_range_flagged(api):
+    """Split fluxes beyond the range of the weights' form (1e26 in fp64, 1e17 in fp32) are
+    reported in debug mode; a state just inside passes (scale invariance: rho and p scaled by
+    s at fixed velocity scale every flux by s)."""
+    import torch
+    from paper_2004_07954_amd import _lib
+    print("[gpu-case] debug range", flush=True)
+    base = _cons(1.0 + 0.1 * np.sin(np.linspace(0, 6, 500)), 0.3, 1.0)
+    dbg = api.params("euler", debug_nonfinite=True)
+    api.rhs_1d(to_dev(base * 1e24), 0.01, dbg)  # max |F| + alpha max |U| ~ 1e25
+    with pytest.raises(_lib.WznError) as e:
+        api.rhs_1d(to_dev(base * 1e27), 0.01, dbg)
+    assert e.value.code == _lib.WZN_ERR_RANGE
+    adv = api.params("advection", bc="periodic", debug_nonfinite=True)
+    a0 = np.sin(np.linspace(0, 6, 300))[None, :]
+    api.rhs_1d(to_dev(a0 * 1e25), 0.01, adv)
+    with pytest.raises(_lib.WznError) as e:
+        api.rhs_1d(to_dev(a0 * 1e26), 0.01, adv)
+    assert e.value.code == _lib.WZN_ERR_RANGE
+    U, dx, dy = I.riemann_2d(1, 32)
+    p32 = api.params("euler", dtype="fp32", eps=1e-30, debug_nonfinite=True)
+    api.rhs_2d(to_dev(U * 1e15, torch.float32), dx, dy, p32)
+    with pytest.raises(_lib.WznError) as e:
+        api.rhs_2d(to_dev(U * 1e18, torch.float32), dx, dy, p32)
+    assert e.value.code == _lib.WZN_ERR_RANGE

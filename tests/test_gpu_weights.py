@@ -171,6 +171,34 @@ def test_reconstruct_sizes(api):
 
 
 @pytest.mark.parametrize("weights,scheme", [("zn", 0), ("z", 1)])
+def test_reconstruct_range_edge(api, orc, weights, scheme):
+    """Stencils whose largest value is exactly 1e26, the stated limit of the fp64 form: the
+    worst windows of its largest product (the alternating sequence, which a host emulation of
+    the form shows overflowing from about 1.1e27; a step, from about 5e27), a ramp, spikes and
+    random stencils rescaled to max |f| = 1e26, with both signs.  All outputs finite and within
+    1e-13 of the stencil scale of the oracle's literal form."""
+    note("reconstruct at the range edge", weights)
+    W = 1e26
+    rows = [[-W, W, -W, W, -W], [W, -W, W, -W, W], [0, 0, 0, W, W], [-W, -W, -W, W, W],
+            [-W, -W / 2, 0, W / 2, W], [W, W / 2, 0, -W / 2, -W], [0, 0, W, 0, 0],
+            [-W, -W, W, -W, -W], [W, -W, -W, -W, W], [W, W, W, W, W]]
+    rng = np.random.default_rng(97 + scheme)
+    rnd = rng.standard_normal((5, 200))
+    rnd *= W / np.abs(rnd).max(axis=0)
+    f = np.concatenate([np.array(rows, dtype=np.float64).T, rnd], axis=1)
+    f = np.ascontiguousarray(np.concatenate([f, -f], axis=1))
+    m = f.shape[1]
+    g = api.reconstruct(to_dev(f), api.params("euler", weights=weights)).cpu().numpy()
+    prm = orc.params(scheme=scheme, q=1)
+    r = np.array([orc.reconstruct(f[:, i], prm)["fhat"] for i in range(m)])
+    scale = np.abs(f).max(axis=0)
+    assert np.isfinite(g).all()
+    err = np.max(np.abs(g - r) / scale)
+    print("range edge: worst error / stencil scale %.2e" % err)
+    assert err <= 1e-13
+
+
+@pytest.mark.parametrize("weights,scheme", [("zn", 0), ("z", 1)])
 @pytest.mark.parametrize("s", [1e-30, 1e-12, 1e12, 1e20])
 def test_reconstruct_extreme_magnitudes(api, orc, weights, scheme, s):
     """The single-divide form keeps its products inside the fp64 range for window values up
