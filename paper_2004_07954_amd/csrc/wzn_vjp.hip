@@ -55,7 +55,11 @@ __device__ __forceinline__ void wzn_grad(const double* v, double nu, double eps,
   const double a = v[0], b = v[1], c = v[2], d = v[3], e = v[4];
   const double A0 = a - 2.0 * b + c, B0 = a - 4.0 * b + 3.0 * c;
   const double A1 = b - 2.0 * c + d, B1 = b - d;
-  const double A2 = c - 2.0 * d + e, B2 = 3.0 * c - 4.0 * d + e;
+  // IS2 as the mirror image of IS0 (the same expression read from e back to c), so that a
+  // stencil symmetric about its centre gives IS0 == IS2, hence tau5 = 0, exactly in floating
+  // point as in exact arithmetic: the forward kernels' difference form has this property, and
+  // the linearisation must see the same tau5 (d|x|/dx at 0 is taken as 0)
+  const double A2 = e - 2.0 * d + c, B2 = e - 4.0 * d + 3.0 * c;
   const double IS0 = (13.0 / 12.0) * A0 * A0 + 0.25 * B0 * B0;
   const double IS1 = (13.0 / 12.0) * A1 * A1 + 0.25 * B1 * B1;
   const double IS2 = (13.0 / 12.0) * A2 * A2 + 0.25 * B2 * B2;

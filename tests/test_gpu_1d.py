@@ -7,6 +7,7 @@ Tolerances (normwise per component, the reading of "relative 1e-12 per RHS evalu
 import numpy as np
 import pytest
 
+from conftest import record
 from paper_2004_07954_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
@@ -158,7 +159,7 @@ def test_euler_run_through_shock_envelope(api, orc):
     api.rk3_run_1d(ug, dx, 150, cfl=0.5)
     ref, env = _perturbed_envelope(orc, u0, dx, 150)
     err = normwise(ug.cpu().numpy(), ref)
-    print("gpu-oracle %.3e, oracle rounding envelope %.3e" % (err, env))
+    record("1D Euler N=4096 150 steps through the shock", gpu_oracle=err, envelope=env)
     assert err <= max(10.0 * env, RUN_TOL)
     u = ug.cpu().numpy()
     assert u[0].min() > 0 and (u[2] - 0.5 * u[1] ** 2 / u[0]).min() > 0
@@ -242,6 +243,46 @@ def test_full_size_conservation(api):
     assert rho.min() > 0 and (E - 0.5 * m * m / rho).min() > 0
     # dt of step 0 from the left state (max |u| + c = 4.5660 ...)
     assert float(dth[0].cpu()) == pytest.approx(0.5 * dx / 4.56603, rel=1e-4)
+
+
+def _oracle_run_chunked(orc, u0, dx, nsteps, progress, label, chunk=200):
+    """The oracle's CFL run in chunks of steps (the same run: dt comes from each step's U^n),
+    with a progress line per chunk."""
+    u, dts = u0, []
+    for s0 in range(0, nsteps, chunk):
+        u, d, _ = orc.rk3_run_1d(u, dx, min(chunk, nsteps - s0), cfl=0.5)
+        dts.append(d)
+        progress("%s: oracle step %d of %d" % (label, s0 + len(d), nsteps))
+    return u, np.concatenate(dts)
+
+
+@pytest.mark.timeout(1200)
+def test_full_size_run_against_oracle(api, orc, progress):
+    """The benchmark workload's whole run (N = 2^20, 1000 steps, the benchmark's launch
+    configuration) against the oracle's run, with the dt history.  The discontinuity at
+    x = -4 moves through the sine wave for the whole run, where the discrete solution
+    amplifies rounding (reading R23), so the bound is the larger of 1e-10 and ten times the
+    oracle's own envelope: its distance to an oracle run from the initial state perturbed by
+    1e-15 relative."""
+    import torch
+    n, nsteps = 1 << 20, 1000
+    note("full size N=2^20 x1000 vs oracle")
+    u0, dx = I.shu_osher_like(n)
+    ug = to_dev(u0)
+    dtg, _ = api.rk3_run_1d(ug, dx, nsteps, cfl=0.5, record=True)
+    torch.cuda.synchronize()
+    g = ug.cpu().numpy()
+    dtg = dtg.cpu().numpy()
+    ref, dtr = _oracle_run_chunked(orc, u0, dx, nsteps, progress, "C2 reference")
+    err = normwise(g, ref)
+    dterr = float(np.max(np.abs(dtg / dtr - 1.0)))
+    xi = np.random.default_rng(1).standard_normal(u0.shape)
+    up, _ = _oracle_run_chunked(orc, u0 * (1 + 1e-15 * xi), dx, nsteps, progress,
+                                "C2 perturbed")
+    env = normwise(up, ref)
+    record("C2 N=2^20 1000 steps", gpu_oracle=err, envelope=env, dt_rel=dterr)
+    assert err <= max(10.0 * env, RUN_TOL), (err, env)
+    assert dterr <= 1e-12
 
 
 def test_bad_arguments(api):

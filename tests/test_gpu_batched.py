@@ -7,6 +7,7 @@ are checked against the CPU oracle (normwise 1e-10 after a short run through the
 import numpy as np
 import pytest
 
+from conftest import record
 from paper_2004_07954_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
@@ -101,11 +102,10 @@ def test_batched_order_and_blocks_invariance(api):
 UNSTABLE = {1767}
 
 
-def test_batched_full_workload_sampled(api):
-    """The benchmark workload (4096 instances, N_i in [256, 16384], seed 4) for 500 steps in
-    the launch configuration the benchmark times (autotuned): a sample of instances is re-run
-    one by one through the single-instance path and must match bit for bit (including the
-    unstable instance's NaNs); every other instance stays finite with rho, p > 0."""
+@pytest.fixture(scope="module")
+def c4_run(api):
+    """The benchmark workload (4096 instances, N_i in [256, 16384], seed 4) advanced 500 steps
+    in the launch configuration the benchmark times (autotuned, longest first)."""
     import torch
     from paper_2004_07954_amd import autotune
     note("batched full workload 4096 x 500")
@@ -115,9 +115,17 @@ def test_batched_full_workload_sampled(api):
     dxg = torch.tensor(dx, dtype=torch.float64, device="cuda")
     order = api.lpt_order(np.diff(offs))
     tn, _ = autotune.tune_batched(Ug, offg, dxg, order=order)
-    api.batched_rk3_run_1d(Ug, offg, dxg, 500, order=order, tuning=tn)
+    dtb = api.batched_rk3_run_1d(Ug, offg, dxg, 500, order=order, tuning=tn, record=True)
     torch.cuda.synchronize()
-    Ub = Ug.cpu().numpy()
+    return U, offs, dx, Ug.cpu().numpy(), dtb.cpu().numpy()
+
+
+def test_batched_full_workload_sampled(api, c4_run):
+    """A sample of instances of the full workload is re-run one by one through the
+    single-instance path and must match bit for bit (including the unstable instance's NaNs);
+    every other instance stays finite with rho, p > 0."""
+    import torch
+    U, offs, dx, Ub, _ = c4_run
     rho, m, E = Ub
     with np.errstate(invalid="ignore", divide="ignore"):
         p = 0.4 * (E - 0.5 * m * m / rho)
@@ -132,6 +140,39 @@ def test_batched_full_workload_sampled(api):
         np.testing.assert_array_equal(Ub[:, sl], u1.cpu().numpy())
 
 
+def test_batched_sampled_against_oracle(orc, c4_run, progress):
+    """Eight instances of the full workload (drawn with a fixed seed from the stable ones)
+    after all 500 steps of the batched launch against the oracle's run of each instance, with
+    the dt histories.  Each shock tube carries its discontinuities through the whole run, where
+    the discrete solution amplifies rounding, so the bound is the larger of 1e-10 and ten times
+    the oracle's own envelope: its distance to oracle runs from the initial state perturbed
+    by 1e-15 relative (two draws)."""
+    U, offs, dx, Ub, dtb = c4_run
+    stable = np.setdiff1d(np.arange(4096), sorted(UNSTABLE))
+    sample = np.random.default_rng(8).choice(stable, 8, replace=False)
+    worst = (0.0, 0.0, 0)
+    for b in sample:
+        sl = slice(offs[b], offs[b + 1])
+        u0 = np.ascontiguousarray(U[:, sl])
+        progress("batched instance %d (N = %d) vs oracle, 500 steps" % (b, u0.shape[1]))
+        ref, dtr, _ = orc.rk3_run_1d(u0, dx[b], 500, cfl=0.5)
+        env = 0.0
+        for sd in (1, 2):
+            xi = np.random.default_rng(sd).standard_normal(u0.shape)
+            up, _, _ = orc.rk3_run_1d(u0 * (1 + 1e-15 * xi), dx[b], 500, cfl=0.5)
+            env = max(env, normwise(up, ref))
+        err = normwise(Ub[:, sl], ref)
+        dterr = float(np.max(np.abs(dtb[b] / dtr - 1.0)))
+        record("C4 instance %d N=%d 500 steps" % (b, u0.shape[1]), gpu_oracle=err,
+               envelope=env, dt_rel=dterr)
+        assert err <= max(10.0 * env, RUN_TOL), (b, err, env)
+        assert dterr <= max(10.0 * env, 1e-12), (b, dterr)
+        if err > worst[0]:
+            worst = (err, env, int(b))
+    record("C4 sampled instances, worst", gpu_oracle=worst[0], envelope=worst[1],
+           instance=worst[2])
+
+
 def test_batched_bad_arguments(api):
     import torch
     from paper_2004_07954_amd._lib import WznError
@@ -142,3 +183,32 @@ def test_batched_bad_arguments(api):
         api.batched_rk3_run_1d(Ug, offg, dxg, 2, tuning=api.batch_tuning(64, 2, 0, 1))
     with pytest.raises(WznError):
         api.batched_rk3_run_1d(Ug, offg, dxg, 2, prm=api.params("euler", lf_alpha=1.0))
+    # the binding rejects an order that is not a permutation and decreasing offsets
+    with pytest.raises(ValueError):
+        api.batched_rk3_run_1d(Ug, offg, dxg, 2, order=torch.tensor([0, 0], dtype=torch.int32,
+                                                                    device="cuda"))
+    with pytest.raises(ValueError):
+        api.batched_rk3_run_1d(Ug, torch.tensor([0, 25, 30], dtype=torch.int64, device="cuda")
+                               .flip(0).contiguous(), dxg, 2)
+
+
+def test_batched_order_out_of_range_skipped(api):
+    """Called through the C ABI directly (past the binding's check), an order entry outside
+    0 .. batch-1 is skipped by the kernel: the instance it names runs, nothing else changes."""
+    import ctypes as C
+    import torch
+    from paper_2004_07954_amd import _lib
+    note("batched order entry out of range")
+    U, offs, dx, Ug, offg, dxg = make_batch([30, 20], seed=3)
+    order = torch.tensor([1, 7], dtype=torch.int32, device="cuda")
+    stage = torch.empty((2, 3, Ug.shape[1]), dtype=torch.float64, device="cuda")
+    prm = api.params("euler")
+    _lib.check(_lib.lib().wzn_batched_rk3_run_1d(
+        C.byref(prm), api._ptr(Ug), api._ptr(stage), Ug.shape[1], api._ptr(offg),
+        api._ptr(dxg), api._ptr(order), 2, 3, 0.5, None, None,
+        api._ptr(api.workspace(Ug.device)), api._stream()))
+    out = Ug.cpu().numpy()
+    np.testing.assert_array_equal(out[:, :30], U[:, :30])  # instance 0 never handed out
+    u1 = torch.tensor(np.ascontiguousarray(U[:, 30:]), dtype=torch.float64, device="cuda")
+    api.rk3_run_1d(u1, dx[1], 3, cfl=0.5)
+    np.testing.assert_array_equal(out[:, 30:], u1.cpu().numpy())
