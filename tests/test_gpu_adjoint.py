@@ -214,6 +214,7 @@ def _c5_complex_run(orc, u0, dx, dts, als, drho):
     return orc.rk3_run_1d_complex(z, dx, dts, als, bc=orc.BC_PERIODIC)
 
 
+@pytest.mark.timeout(600)
 def test_adjoint_c5_complex_step(api, orc, c5_oracle, progress):
     """The adjoint workload's gradient (N = 65536, 400 steps, checkpoints every 20) pinned by
     complex-step directional derivatives of the oracle's run with its own frozen schedule

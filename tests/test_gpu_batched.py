@@ -140,6 +140,7 @@ def test_batched_full_workload_sampled(api, c4_run):
         np.testing.assert_array_equal(Ub[:, sl], u1.cpu().numpy())
 
 
+@pytest.mark.timeout(600)
 def test_batched_sampled_against_oracle(orc, c4_run, progress):
     """Eight instances of the full workload (drawn with a fixed seed from the stable ones)
     after all 500 steps of the batched launch against the oracle's run of each instance, with
