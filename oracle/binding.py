@@ -63,6 +63,8 @@ def lib():
                                            d, d]
         L.orc_rk3_run_1d_c128.argtypes = [i32, i32, i64, p, d, C.c_int32, p, p,
                                           C.POINTER(OrcParams), d, d]
+        L.orc_rk3_run_1d_f128.argtypes = [i32, i32, i64, p, p, d, C.c_int32, p, p,
+                                          C.POINTER(OrcParams), d, d]
         L.orc_rhs_2d_f64.argtypes = [i32, i32, i64, i64, p, p, d, d, d, d,
                                      C.POINTER(OrcParams), d, p]
         L.orc_rk3_run_2d_f64.argtypes = [i32, i32, i64, i64, p, d, d, d, C.c_int32, p,
@@ -200,6 +202,21 @@ def rk3_run_1d_complex(u, dx, dts, alphas, sys=SYS_EULER1, bc=BC_PERIODIC, prm=N
     lib().orc_rk3_run_1d_c128(sys, bc, n, _ptr(u), dx, int(dts.size), _ptr(dts), _ptr(al),
                               C.byref(prm), a, gamma)
     return u
+
+
+def rk3_run_1d_f128(u_hi, u_lo, dx, dts, alphas, sys=SYS_EULER1, bc=BC_PERIODIC, prm=None,
+                    a=1.0, gamma=GAMMA):
+    """len(dts) TVD-RK3 steps in __float128 with the frozen schedule dts [nsteps], alphas
+    [nsteps, 3]; the state as (hi, lo) pairs.  Returns (hi, lo)."""
+    prm = prm or params()
+    uh, ul = _f64(u_hi).copy(), _f64(u_lo).copy()
+    n = uh.shape[-1]
+    dts = _f64(dts).reshape(-1)
+    al = _f64(alphas).reshape(-1)
+    assert al.size == 3 * dts.size and ul.shape == uh.shape
+    lib().orc_rk3_run_1d_f128(sys, bc, n, _ptr(uh), _ptr(ul), dx, int(dts.size), _ptr(dts),
+                              _ptr(al), C.byref(prm), a, gamma)
+    return uh, ul
 
 
 def rhs_2d(u, dx, dy, bcx=BC_TRANSMISSIVE, bcy=BC_TRANSMISSIVE, alpha_x=-1.0, alpha_y=-1.0,

@@ -773,6 +773,35 @@ void orc_rk3_run_1d_c128(int sys, int bc, int64_t n, double* u_ri, double dx, in
     orc_rk3_step_1d_c128(sys, bc, n, u_ri, dx, dts[s], alphas + 3 * s, P, a, gamma);
 }
 
+// ---- nsteps TVD-RK3 steps in __float128 with the frozen schedule dts[nsteps],
+// alphas[nsteps][3] (reference values of a whole run below fp64 resolution, e.g. finite
+// differences with steps far below the fp64 spacing of the state).  The state is carried in
+// __float128 between steps; input and output as (hi, lo) pairs, value = hi + lo.
+void orc_rk3_run_1d_f128(int sys, int bc, int64_t n, double* uhi, double* ulo, double dx,
+                         int32_t nsteps, const double* dts, const double* alphas,
+                         const OrcParams* P, double a, double gamma) {
+  Phys ph{a, gamma};
+  const int nv = nvar_of(sys);
+  const int64_t M = nv * n;
+  std::vector<f128> un(M), us(M), L(M);
+  for (int64_t k = 0; k < M; ++k) un[k] = (f128)uhi[k] + (f128)ulo[k];
+  const f128 rk_a[3] = {f128(0), f128(3) / f128(4), f128(1) / f128(3)};
+  const f128 rk_b[3] = {f128(1), f128(1) / f128(4), f128(2) / f128(3)};
+  for (int32_t st = 0; st < nsteps; ++st) {
+    us = un;
+    const f128 dt = (f128)dts[st];
+    for (int s = 0; s < 3; ++s) {
+      rhs_1d<f128>(sys, bc, n, us.data(), L.data(), (f128)dx, alphas[3 * st + s], *P, ph);
+      for (int64_t k = 0; k < M; ++k) us[k] = rk_a[s] * un[k] + rk_b[s] * (us[k] + dt * L[k]);
+    }
+    un = us;
+  }
+  for (int64_t k = 0; k < M; ++k) {
+    uhi[k] = (double)un[k];
+    ulo[k] = (double)(un[k] - (f128)uhi[k]);
+  }
+}
+
 // ---- 2D RHS (fp64).  alpha_x/alpha_y < 0: compute from u.  Returns both alphas.
 void orc_rhs_2d_f64(int bcx, int bcy, int64_t nx, int64_t ny, const double* u, double* dudt,
                     double dx, double dy, double alpha_x, double alpha_y, const OrcParams* P,

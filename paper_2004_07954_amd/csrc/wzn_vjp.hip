@@ -9,8 +9,8 @@
 // and the Euler flux Jacobian, and through the boundary index map (ghost cells add their
 // cotangent to the cell they copy).
 //
-// One workgroup owns a tile of NT output cells.  It stages the split fluxes of the cells
-// the tile's interfaces read (tile +- 5 cells) and the cotangents mu (tile -3 .. +2) in LDS,
+// One workgroup owns a run of interfaces, one per thread, and the cells between them.  It
+// stages the split fluxes of the cells the interfaces read and the cotangents mu in LDS,
 // computes per interface the ten scaled partial derivatives nu_e * d fhat_e / d f^{+-}(cell),
 // and each output cell then gathers the partials of the (at most six) interfaces whose
 // stencils contain it.
@@ -139,111 +139,138 @@ __device__ __forceinline__ int64_t map_cell(int64_t p, int64_t n, int bc) {
   return p < 0 ? 0 : n - 1;
 }
 
-// One workgroup of 256 threads per tile of TC = 64 output cells; every phase spreads its
-// (component, interface) or (component, cell) tasks over the threads.
-constexpr int VJP_TC = 64;
+// One workgroup of VJP_NT threads owns VJP_NT interfaces, e = g0 - 3 + t for thread t (the right
+// interface of cell e), and the VJP_NT - 5 cells g0 .. g0 + VJP_NT - 6 whose six interfaces
+// (e = j - 3 .. j + 2) all lie among them; tiles overlap by five interfaces.  Every load of a
+// thread is issued at kernel start: the split fluxes and states of the cells the interfaces'
+// stencils read (g0 - 5 .. g0 + VJP_NT - 1; threads 0..4 take the last five), the cotangents
+// mu of g0 - 3 .. g0 + VJP_NT - 3, and the cell's own accumulator.  Then, component by
+// component, each thread forms the ten scaled partials of its interface's two reconstructions
+// and publishes them in LDS, and each cell gathers the partials of the stencil positions that
+// are that cell.
 constexpr int VJP_NT = 256;
+constexpr int VJP_TC = VJP_NT - 5;  // output cells per workgroup
 
 __global__ __launch_bounds__(VJP_NT) void vjp_kernel(VjpArgs a) {
-  constexpr int TC = VJP_TC;
-  constexpr int NW = TC + 10;  // staged split-flux cells: g0-5 .. g0+TC+4
-  constexpr int NM = TC + 6;   // staged cotangent cells:  g0-3 .. g0+TC+2
-  constexpr int NI = TC + 5;   // interfaces (right interface of cell e): e = g0-3 .. g0+TC+1
-  __shared__ double Wp[3][NW], Wm[3][NW], MU[3][NM], G[3][10][NI], WB[3][2][TC];
+  constexpr int NT = VJP_NT, TC = VJP_TC;
+  constexpr int NW = NT + 5;  // staged cells g0 - 5 .. g0 + NT - 1
+  constexpr int NM = NT + 1;  // staged cotangents g0 - 3 .. g0 + NT - 3
+  __shared__ double Wp[3][NW], Wm[3][NW], US[3][NW], MU[3][NM], G[10][NT];
   const int tid = threadIdx.x;
   const int64_t n = a.n;
   const int64_t g0 = (int64_t)blockIdx.x * TC;
   const double alpha = a.alpha_arr ? a.alpha_arr[0] : a.alpha_const;
   const double gm1 = a.gamma - 1.0;
+  const int64_t j = g0 + tid;  // this thread's output cell (tid < TC)
+  const bool own = tid < TC && j < n;
 
-  if (tid < NW) {
-    const int i = tid;
-    const int64_t cell = map_cell(g0 - 5 + i, n, a.bc);
-    const double rho = a.U[cell], m = a.U[n + cell], E = a.U[2 * n + cell];
-    const double u = m / rho;
-    const double p = gm1 * (E - 0.5 * rho * u * u);
-    const double F[3] = {rho * u, rho * u * u + p, u * (E + p)};
-    const double Uc[3] = {rho, m, E};
+  // ---- every load first
+  double Uc[2][3], muv[2][3], accv[3] = {0.0, 0.0, 0.0};
+  const int nld = tid < 5 ? 2 : 1;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      Wp[c][i] = 0.5 * (F[c] + alpha * Uc[c]);
-      Wm[c][i] = 0.5 * (F[c] - alpha * Uc[c]);
+  for (int r = 0; r < 2; ++r) {
+    if (r < nld) {
+      const int i = r == 0 ? tid : NT + tid;
+      const int64_t cell = map_cell(g0 - 5 + i, n, a.bc);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) Uc[r][c] = a.U[c * n + cell];
     }
-  } else if (tid >= 128 && tid < 128 + NM) {
-    const int i = tid - 128;
-    const int64_t cell = g0 - 3 + i;
-    int64_t src = -1;
-    if (a.bc == 0) src = map_cell(cell, n, 0);
-    else if (cell >= 0 && cell < n) src = cell;
+  }
 #pragma unroll
-    for (int c = 0; c < 3; ++c) MU[c][i] = src >= 0 ? a.mu[c * n + src] : 0.0;
+  for (int r = 0; r < 2; ++r) {
+    if (r == 0 || tid == 0) {
+      const int i = r == 0 ? tid : NT;
+      const int64_t cell = g0 - 3 + i;
+      int64_t src = -1;
+      if (a.bc == 0) src = map_cell(cell, n, 0);
+      else if (cell >= 0 && cell < n) src = cell;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) muv[r][c] = src >= 0 ? a.mu[c * n + src] : 0.0;
+    }
+  }
+  if (own && a.stage_mode && a.acc_in) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) accv[c] = a.acc_in[c * n + j];
+  }
+  // ---- split fluxes (and states) of the staged cells, cotangents
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    if (r < nld) {
+      const int i = r == 0 ? tid : NT + tid;
+      const double rho = Uc[r][0], m = Uc[r][1], E = Uc[r][2];
+      const double u = m / rho;
+      const double p = gm1 * (E - 0.5 * rho * u * u);
+      const double F[3] = {rho * u, rho * u * u + p, u * (E + p)};
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        Wp[c][i] = 0.5 * (F[c] + alpha * Uc[r][c]);
+        Wm[c][i] = 0.5 * (F[c] - alpha * Uc[r][c]);
+        US[c][i] = Uc[r][c];
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    MU[c][tid] = muv[0][c];
+    if (tid == 0) MU[c][NT] = muv[1][c];
   }
   __syncthreads();
 
-  // (component, interface) tasks: nu_e times the partials of the two reconstructions
-  if (tid < 3 * NI) {
-    const int c = tid / NI, i = tid - c * NI;
-    const int64_t e = g0 - 3 + i;
-    const bool valid = a.bc == 0 || (e >= -1 && e <= n - 1);
-    const double nu = valid ? (MU[c][i + 1] - MU[c][i]) * (1.0 / a.dx) : 0.0;
+  // ---- per component: nu_e times the partials of the interface's two reconstructions,
+  //      published in G[k][t] (k = 0..4: f^+ stencil cells e-2 .. e+2; 5..9: f^- stencil
+  //      cells e+3 .. e-1), then gathered by the cells
+  const int64_t e = g0 - 3 + tid;
+  const bool valid = a.bc == 0 || (e >= -1 && e <= n - 1);
+  const bool interior = j >= 5 && j + 5 < n;
+  double wbp[3], wbm[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double nu = valid ? (MU[c][tid + 1] - MU[c][tid]) * (1.0 / a.dx) : 0.0;
     double v[5], gp[5], gmv[5];
 #pragma unroll
-    for (int k = 0; k < 5; ++k) v[k] = Wp[c][i + k];  // cells e-2 .. e+2
+    for (int k = 0; k < 5; ++k) v[k] = Wp[c][tid + k];  // cells e-2 .. e+2
     wzn_grad(v, nu, a.eps, a.A, gp);
 #pragma unroll
-    for (int k = 0; k < 5; ++k) v[k] = Wm[c][i + 5 - k];  // cells e+3 .. e-1
+    for (int k = 0; k < 5; ++k) v[k] = Wm[c][tid + 5 - k];  // cells e+3 .. e-1
     wzn_grad(v, nu, a.eps, a.A, gmv);
+    if (c > 0) __syncthreads();  // the previous component's gather has read G
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      G[c][k][i] = gp[k];
-      G[c][5 + k][i] = gmv[k];
+      G[k][tid] = gp[k];
+      G[5 + k][tid] = gmv[k];
     }
-  }
-  __syncthreads();
-
-  // (component, cell) tasks: gather the partials of the interfaces whose stencils hold the cell
-  if (tid < 3 * TC) {
-    const int c = tid / TC, t = tid - c * TC;
-    const int64_t j = g0 + t;
+    __syncthreads();
     double sp = 0.0, sm = 0.0;
-    if (j < n) {
-      const int base = t + 3;  // interface slot of e = j
-      if (j >= 5 && j + 5 < n) {
-        // interior: cell j is slot 2 - de of the f^+ stencil and slot 3 + de of the f^-
-        // stencil of interface e = j + de
+    if (own) {
+      if (interior) {
+        // cell j is slot k of the f^+ stencil of interface j + 2 - k (thread tid + 5 - k) and
+        // slot 5 + k of the f^- stencil of interface j - 3 + k (thread tid + k)
 #pragma unroll
-        for (int de = -3; de <= 2; ++de) {
-          if (de >= -2) sp += G[c][2 - de][base + de];
-          if (de <= 1) sm += G[c][5 + 3 + de][base + de];
+        for (int k = 0; k < 5; ++k) {
+          sp += G[k][tid + 5 - k];
+          sm += G[5 + k][tid + k];
         }
       } else {
+        // near the ends of the row: every stencil slot that the boundary index map sends to j
         for (int de = -3; de <= 2; ++de) {
-          const int64_t e = j + de;
+          const int64_t ee = j + de;
+          const int slot = tid + 3 + de;
 #pragma unroll
           for (int k = 0; k < 5; ++k) {
-            if (map_cell(e - 2 + k, n, a.bc) == j) sp += G[c][k][base + de];
-            if (map_cell(e + 3 - k, n, a.bc) == j) sm += G[c][5 + k][base + de];
+            if (map_cell(ee - 2 + k, n, a.bc) == j) sp += G[k][slot];
+            if (map_cell(ee + 3 - k, n, a.bc) == j) sm += G[5 + k][slot];
           }
         }
       }
     }
-    WB[c][0][t] = sp;
-    WB[c][1][t] = sm;
+    wbp[c] = sp;
+    wbm[c] = sm;
   }
-  __syncthreads();
+  if (!own) return;
 
-  if (tid >= TC) return;
-  const int64_t j = g0 + tid;
-  if (j >= n) return;
-  double wbp[3], wbm[3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    wbp[c] = WB[c][0][tid];
-    wbm[c] = WB[c][1][tid];
-  }
   // f^{+-}_c = (F_c +- alpha U_c)/2:  Ubar_d = 1/2 sum_c (wbp_c + wbm_c) dF_c/dU_d
   //                                          + alpha/2 (wbp_d - wbm_d)
-  const double rho = a.U[j], m = a.U[n + j], E = a.U[2 * n + j];
+  const double rho = US[0][tid + 5], m = US[1][tid + 5], E = US[2][tid + 5];
   const double u = m / rho;
   const double p = gm1 * (E - 0.5 * rho * u * u);
   const double H = (E + p) / rho;
@@ -267,9 +294,9 @@ __global__ __launch_bounds__(VJP_NT) void vjp_kernel(VjpArgs a) {
       a.out[gi] = Ub[c];
     } else {
       const double dt = a.dt_arr[0];
-      const double mu_j = a.mu[gi];
+      const double mu_j = MU[c][tid + 3];
       const double v = mu_j + dt * Ub[c];
-      const double ain = a.acc_in ? a.acc_in[gi] : 0.0;
+      const double ain = accv[c];
       a.out[gi] = a.p * v + a.q * ain;
       if (a.acc_out) a.acc_out[gi] = a.r * ain + a.s * mu_j;
     }
