@@ -47,6 +47,13 @@ struct VjpArgs {
   double p, q, r, s;
 };
 
+// 1/x from one v_rcp_f64 (relative error up to ~5e-8) and one Newton step (~2e-15): enough
+// for a derivative that is compared at 1e-10.
+__device__ __forceinline__ double rcp1(double x) {
+  const double r = __builtin_amdgcn_rcp(x);
+  return __builtin_fma(__builtin_fma(-x, r, 1.0), r, r);
+}
+
 // f-hat of one reconstruction (Sec. 2.1 eq:3-5, Sec. 3 eq:function, eq:tau8, eq:new) and
 // g[k] = nu * d fhat / d v[k], evaluated in the paper's literal form (fp64 carries the
 // magnitudes of C and tau8/(IS_k+eps) for eps = 1e-40).  d|x|/dx is taken as 0 at x = 0.
@@ -68,7 +75,7 @@ __device__ __forceinline__ void wzn_grad(const double* v, double nu, double eps,
   const double diff = IS0 - IS2;
   const double t5 = __builtin_fabs(diff);
   const double num = IS0 + IS2 - t5 + eps, den = t5 + eps;
-  const double iden = fast_div(1.0, den);
+  const double iden = rcp1(den);
   const double r = num * iden;
   const double C = A * r * r;
   const double ck[3] = {0.1, 0.6, 0.3};
@@ -77,12 +84,12 @@ __device__ __forceinline__ void wzn_grad(const double* v, double nu, double eps,
   double S = 0.0;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    is[k] = fast_div(1.0, s[k]);
+    is[k] = rcp1(s[k]);
     t[k] = tau8 * is[k];
     al[k] = ck[k] * (C + t[k]);
     S += al[k];
   }
-  const double iS = fast_div(1.0, S);
+  const double iS = rcp1(S);
   // q_k - q_1 from second differences (eq:4): no cancellation of the O(f) parts
   const double dq[3] = {(A0 - A1) * (1.0 / 3.0), 0.0, (A1 - A2) * (1.0 / 6.0)};
   double tbar = 0.0;
@@ -128,149 +135,142 @@ __device__ __forceinline__ void wzn_grad(const double* v, double nu, double eps,
   g[4] = d4b + A2b + B2b - qb2 * (1.0 / 6.0);
 }
 
-// Boundary index map: periodic wrap or transmissive clamp of any cell index p (the integer
-// division only runs for indices outside the grid).
+// Boundary index map: periodic wrap or transmissive clamp of any cell index p.  Indices
+// within one period of the grid wrap by one addition; the 64-bit remainder (a long software
+// sequence on the GPU) only runs further out, for rows shorter than a tile.
 __device__ __forceinline__ int64_t map_cell(int64_t p, int64_t n, int bc) {
   if (p >= 0 && p < n) return p;
-  if (bc == 0) {
-    p %= n;
-    return p < 0 ? p + n : p;
-  }
-  return p < 0 ? 0 : n - 1;
+  if (bc != 0) return p < 0 ? 0 : n - 1;
+  if (p < 0 && p >= -n) return p + n;
+  if (p >= n && p < 2 * n) return p - n;
+  p %= n;
+  return p < 0 ? p + n : p;
 }
 
-// One workgroup of VJP_NT threads owns VJP_NT interfaces, e = g0 - 3 + t for thread t (the right
-// interface of cell e), and the VJP_NT - 5 cells g0 .. g0 + VJP_NT - 6 whose six interfaces
-// (e = j - 3 .. j + 2) all lie among them; tiles overlap by five interfaces.  Every load of a
-// thread is issued at kernel start: the split fluxes and states of the cells the interfaces'
-// stencils read (g0 - 5 .. g0 + VJP_NT - 1; threads 0..4 take the last five), the cotangents
-// mu of g0 - 3 .. g0 + VJP_NT - 3, and the cell's own accumulator.  Then, component by
-// component, each thread forms the ten scaled partials of its interface's two reconstructions
-// and publishes them in LDS, and each cell gathers the partials of the stencil positions that
-// are that cell.
-constexpr int VJP_NT = 256;
-constexpr int VJP_TC = VJP_NT - 5;  // output cells per workgroup
+// One workgroup owns VJP_NI interfaces, e = g0 - 3 + i (the right interface of cell e), and the
+// VJP_NI - 5 cells g0 .. g0 + VJP_NI - 6 whose six interfaces (e = j - 3 .. j + 2) all lie among
+// them; tiles overlap by five interfaces.  One thread per (sign, component, interface) pulls
+// nu_e back through one reconstruction, so that the ~130 instructions of a reconstruction's
+// reverse sweep are spread over six threads per interface (the kernel is short and
+// latency-bound at the adjoint workload's size).  Every global load is issued at kernel start:
+// the states of the cells the stencils read (g0 - 5 .. g0 + VJP_NI - 1), the cotangents mu of
+// g0 - 3 .. g0 + VJP_NI - 3, and the accumulator of the output cells.
+constexpr int VJP_NI = 64;
+constexpr int VJP_NT = 6 * VJP_NI;
+constexpr int VJP_TC = VJP_NI - 5;  // output cells per workgroup
 
 __global__ __launch_bounds__(VJP_NT) void vjp_kernel(VjpArgs a) {
-  constexpr int NT = VJP_NT, TC = VJP_TC;
-  constexpr int NW = NT + 5;  // staged cells g0 - 5 .. g0 + NT - 1
-  constexpr int NM = NT + 1;  // staged cotangents g0 - 3 .. g0 + NT - 3
-  __shared__ double Wp[3][NW], Wm[3][NW], US[3][NW], MU[3][NM], G[10][NT];
+  constexpr int NI = VJP_NI, TC = VJP_TC;
+  constexpr int NW = NI + 5;  // staged cells g0 - 5 .. g0 + NI - 1
+  constexpr int NM = NI + 1;  // staged cotangents g0 - 3 .. g0 + NI - 3
+  __shared__ double Wp[3][NW], Wm[3][NW], US[3][NW], MU[3][NM], G[3][10][NI];
   const int tid = threadIdx.x;
   const int64_t n = a.n;
   const int64_t g0 = (int64_t)blockIdx.x * TC;
   const double alpha = a.alpha_arr ? a.alpha_arr[0] : a.alpha_const;
   const double gm1 = a.gamma - 1.0;
-  const int64_t j = g0 + tid;  // this thread's output cell (tid < TC)
-  const bool own = tid < TC && j < n;
 
-  // ---- every load first
-  double Uc[2][3], muv[2][3], accv[3] = {0.0, 0.0, 0.0};
-  const int nld = tid < 5 ? 2 : 1;
+  // ---- loads: staged states (threads 0 .. NW-1), cotangents (threads 128 .. 128+NM-1),
+  //      accumulator of the output cells (threads 256 .. 256+TC-1)
+  double Uc[3], muv[3], accv[3];
+  const int tm = tid - 128, ta = tid - 256;
+  const int64_t jo = g0 + ta;  // output cell of threads 256 ..
+  if (tid < NW) {
+    const int64_t cell = map_cell(g0 - 5 + tid, n, a.bc);
 #pragma unroll
-  for (int r = 0; r < 2; ++r) {
-    if (r < nld) {
-      const int i = r == 0 ? tid : NT + tid;
-      const int64_t cell = map_cell(g0 - 5 + i, n, a.bc);
+    for (int c = 0; c < 3; ++c) Uc[c] = a.U[c * n + cell];
+  } else if (tm >= 0 && tm < NM) {
+    const int64_t cell = g0 - 3 + tm;
+    int64_t src = -1;
+    if (a.bc == 0) src = map_cell(cell, n, 0);
+    else if (cell >= 0 && cell < n) src = cell;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) Uc[r][c] = a.U[c * n + cell];
+    for (int c = 0; c < 3; ++c) muv[c] = src >= 0 ? a.mu[c * n + src] : 0.0;
+  } else if (ta >= 0 && ta < TC && jo < n && a.stage_mode && a.acc_in) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) accv[c] = a.acc_in[c * n + jo];
+  }
+  if (tid < NW) {
+    const double rho = Uc[0], m = Uc[1], E = Uc[2];
+    const double u = m / rho;
+    const double p = gm1 * (E - 0.5 * rho * u * u);
+    const double F[3] = {rho * u, rho * u * u + p, u * (E + p)};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      Wp[c][tid] = 0.5 * (F[c] + alpha * Uc[c]);
+      Wm[c][tid] = 0.5 * (F[c] - alpha * Uc[c]);
+      US[c][tid] = Uc[c];
     }
-  }
+  } else if (tm >= 0 && tm < NM) {
 #pragma unroll
-  for (int r = 0; r < 2; ++r) {
-    if (r == 0 || tid == 0) {
-      const int i = r == 0 ? tid : NT;
-      const int64_t cell = g0 - 3 + i;
-      int64_t src = -1;
-      if (a.bc == 0) src = map_cell(cell, n, 0);
-      else if (cell >= 0 && cell < n) src = cell;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) muv[r][c] = src >= 0 ? a.mu[c * n + src] : 0.0;
-    }
-  }
-  if (own && a.stage_mode && a.acc_in) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c) accv[c] = a.acc_in[c * n + j];
-  }
-  // ---- split fluxes (and states) of the staged cells, cotangents
-#pragma unroll
-  for (int r = 0; r < 2; ++r) {
-    if (r < nld) {
-      const int i = r == 0 ? tid : NT + tid;
-      const double rho = Uc[r][0], m = Uc[r][1], E = Uc[r][2];
-      const double u = m / rho;
-      const double p = gm1 * (E - 0.5 * rho * u * u);
-      const double F[3] = {rho * u, rho * u * u + p, u * (E + p)};
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        Wp[c][i] = 0.5 * (F[c] + alpha * Uc[r][c]);
-        Wm[c][i] = 0.5 * (F[c] - alpha * Uc[r][c]);
-        US[c][i] = Uc[r][c];
-      }
-    }
-  }
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    MU[c][tid] = muv[0][c];
-    if (tid == 0) MU[c][NT] = muv[1][c];
+    for (int c = 0; c < 3; ++c) MU[c][tm] = muv[c];
   }
   __syncthreads();
 
-  // ---- per component: nu_e times the partials of the interface's two reconstructions,
-  //      published in G[k][t] (k = 0..4: f^+ stencil cells e-2 .. e+2; 5..9: f^- stencil
-  //      cells e+3 .. e-1), then gathered by the cells
-  const int64_t e = g0 - 3 + tid;
-  const bool valid = a.bc == 0 || (e >= -1 && e <= n - 1);
+  // ---- one reconstruction per thread: sign sg, component c, interface slot i.  G[c][k][i]
+  //      holds nu_e d fhat^+_e / d f^+(cell e-2+k) (k = 0..4) and nu_e d fhat^-_e /
+  //      d f^-(cell e+3-(k-5)) (k = 5..9)
+  {
+    const int sg = tid / (3 * NI), c = (tid / NI) % 3, i = tid % NI;
+    const int64_t e = g0 - 3 + i;
+    const bool valid = a.bc == 0 || (e >= -1 && e <= n - 1);
+    const double nu = valid ? (MU[c][i + 1] - MU[c][i]) * (1.0 / a.dx) : 0.0;
+    double v[5], g[5];
+    if (sg == 0) {
+#pragma unroll
+      for (int k = 0; k < 5; ++k) v[k] = Wp[c][i + k];  // cells e-2 .. e+2
+    } else {
+#pragma unroll
+      for (int k = 0; k < 5; ++k) v[k] = Wm[c][i + 5 - k];  // cells e+3 .. e-1
+    }
+    wzn_grad(v, nu, a.eps, a.A, g);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) G[c][5 * sg + k][i] = g[k];
+  }
+  __syncthreads();
+
+  // ---- output cells: gather, flux Jacobian, stage combination
+  if (ta < 0 || ta >= TC || jo >= n) return;
+  const int t = ta;
+  const int64_t j = jo;
   const bool interior = j >= 5 && j + 5 < n;
+  int64_t mc[11];
+  if (!interior) {
+#pragma unroll
+    for (int q = 0; q < 11; ++q) mc[q] = map_cell(j - 5 + q, n, a.bc);
+  }
   double wbp[3], wbm[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const double nu = valid ? (MU[c][tid + 1] - MU[c][tid]) * (1.0 / a.dx) : 0.0;
-    double v[5], gp[5], gmv[5];
-#pragma unroll
-    for (int k = 0; k < 5; ++k) v[k] = Wp[c][tid + k];  // cells e-2 .. e+2
-    wzn_grad(v, nu, a.eps, a.A, gp);
-#pragma unroll
-    for (int k = 0; k < 5; ++k) v[k] = Wm[c][tid + 5 - k];  // cells e+3 .. e-1
-    wzn_grad(v, nu, a.eps, a.A, gmv);
-    if (c > 0) __syncthreads();  // the previous component's gather has read G
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      G[k][tid] = gp[k];
-      G[5 + k][tid] = gmv[k];
-    }
-    __syncthreads();
     double sp = 0.0, sm = 0.0;
-    if (own) {
-      if (interior) {
-        // cell j is slot k of the f^+ stencil of interface j + 2 - k (thread tid + 5 - k) and
-        // slot 5 + k of the f^- stencil of interface j - 3 + k (thread tid + k)
+    if (interior) {
+      // cell j is slot k of the f^+ stencil of interface j + 2 - k (slot t + 5 - k) and slot
+      // 5 + k of the f^- stencil of interface j - 3 + k (slot t + k)
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        sp += G[c][k][t + 5 - k];
+        sm += G[c][5 + k][t + k];
+      }
+    } else {
+      // near the ends of the row: every stencil slot that the boundary index map sends to j
+      // (stencil cells lie within j - 5 .. j + 5; mc[q] is the image of cell j - 5 + q)
+#pragma unroll
+      for (int de = -3; de <= 2; ++de) {
+        const int slot = t + 3 + de;
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
-          sp += G[k][tid + 5 - k];
-          sm += G[5 + k][tid + k];
-        }
-      } else {
-        // near the ends of the row: every stencil slot that the boundary index map sends to j
-        for (int de = -3; de <= 2; ++de) {
-          const int64_t ee = j + de;
-          const int slot = tid + 3 + de;
-#pragma unroll
-          for (int k = 0; k < 5; ++k) {
-            if (map_cell(ee - 2 + k, n, a.bc) == j) sp += G[k][slot];
-            if (map_cell(ee + 3 - k, n, a.bc) == j) sm += G[5 + k][slot];
-          }
+          if (mc[de + k + 3] == j) sp += G[c][k][slot];      // cell j + de - 2 + k
+          if (mc[de - k + 8] == j) sm += G[c][5 + k][slot];  // cell j + de + 3 - k
         }
       }
     }
     wbp[c] = sp;
     wbm[c] = sm;
   }
-  if (!own) return;
 
   // f^{+-}_c = (F_c +- alpha U_c)/2:  Ubar_d = 1/2 sum_c (wbp_c + wbm_c) dF_c/dU_d
   //                                          + alpha/2 (wbp_d - wbm_d)
-  const double rho = US[0][tid + 5], m = US[1][tid + 5], E = US[2][tid + 5];
+  const double rho = US[0][t + 5], m = US[1][t + 5], E = US[2][t + 5];
   const double u = m / rho;
   const double p = gm1 * (E - 0.5 * rho * u * u);
   const double H = (E + p) / rho;
@@ -294,9 +294,9 @@ __global__ __launch_bounds__(VJP_NT) void vjp_kernel(VjpArgs a) {
       a.out[gi] = Ub[c];
     } else {
       const double dt = a.dt_arr[0];
-      const double mu_j = MU[c][tid + 3];
+      const double mu_j = MU[c][t + 3];
       const double v = mu_j + dt * Ub[c];
-      const double ain = accv[c];
+      const double ain = a.acc_in ? accv[c] : 0.0;
       a.out[gi] = a.p * v + a.q * ain;
       if (a.acc_out) a.acc_out[gi] = a.r * ain + a.s * mu_j;
     }
