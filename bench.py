@@ -20,6 +20,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
+# launch-shape layouts of the 1D stage kernel (wzn_set_row_tuning)
+LAYOUT_NAMES = {0: "tile", 1: "split"}
 FP64_VALU_PEAK_TFLOPS = 78.6   # MI355X fp64 vector (FMA = 2 flop)
 
 
@@ -71,25 +73,39 @@ FLOPS_PER_CELL_STAGE = 6 * 86 + 10 + 15 + 9 + 12 + 11
 VALU_LANE_PEAK = 256 * 4 * 16 * 2.4e9  # fp64 VALU lane-instructions/s (FMA = 1 instruction)
 
 
-def cpu_baseline(n, budget_s=12.0):
+def cpu_baseline(n, budget_s=12.0, serial_budget_s=10.0):
     """The oracle as it stands, on the host cores, over a bounded sample of the same
-    workload (whole RK3 steps at the full N)."""
+    workload (whole RK3 steps at the full N): on every host core (the reported value), and
+    serially on one core beside it."""
     import numpy as np  # noqa: F401
     from oracle import binding as orc
     from paper_2004_07954_amd import inputs as I
     u, dx = I.shu_osher_like(n)
     orc.lib()
-    t0 = time.perf_counter()
-    u1, _, _ = orc.rk3_run_1d(u, dx, 1, cfl=0.5)
-    t1 = time.perf_counter() - t0
-    steps = max(1, min(400, int(budget_s / max(t1, 1e-3))))
-    t0 = time.perf_counter()
-    orc.rk3_run_1d(u1, dx, steps, cfl=0.5)
-    el = time.perf_counter() - t0
-    return {"value": n * 3 * steps / el, "unit": "cell-RHS/s", "cores": orc.num_threads(),
+    cores = orc.num_threads()
+
+    def sample(budget):
+        t0 = time.perf_counter()
+        u1, _, _ = orc.rk3_run_1d(u, dx, 1, cfl=0.5)
+        t1 = time.perf_counter() - t0
+        steps = max(1, min(400, int(budget / max(t1, 1e-3))))
+        t0 = time.perf_counter()
+        orc.rk3_run_1d(u1, dx, steps, cfl=0.5)
+        return steps, time.perf_counter() - t0
+
+    steps, el = sample(budget_s)
+    orc.set_num_threads(1)
+    try:
+        steps1, el1 = sample(serial_budget_s)
+    finally:
+        orc.set_num_threads(cores)
+    return {"value": n * 3 * steps / el, "unit": "cell-RHS/s", "cores": cores,
             "kind": "oracle",
             "sample": "%d TVD-RK3 steps (%d RHS evaluations) of the N=%d 1D Euler workload, "
-                      "%.1f s" % (steps, 3 * steps, n, el)}
+                      "%.1f s" % (steps, 3 * steps, n, el),
+            "serial": {"value": n * 3 * steps1 / el1, "unit": "cell-RHS/s", "cores": 1,
+                       "sample": "%d TVD-RK3 steps at N=%d on one thread, %.1f s"
+                                 % (steps1, n, el1)}}
 
 
 def bench_2d(steps, dtype_name, warmup=3, split="lf"):
@@ -204,6 +220,22 @@ def bench_batched(steps, baseline_sample=48, use_graph=True):
     torch.cuda.synchronize()
     ms_sample = s.elapsed_time(e)
     ms_baseline = ms_sample * len(lens) / baseline_sample
+    # the same per-instance launches captured in one HIP graph and replayed: the GPU time of
+    # one launch per instance and stage without the host's launch cost
+    pg = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(pg):
+        for t, stg, b in zip(singles, st1, pick):
+            api.rk3_run_1d(t, float(dx[b]), steps, cfl=0.5, stage=stg)
+    for t, b in zip(singles, pick):
+        t.copy_(torch.tensor(np.ascontiguousarray(U[:, offs[b]:offs[b + 1]]),
+                             dtype=torch.float64, device=dev))
+    torch.cuda.synchronize()
+    s.record()
+    pg.replay()
+    e.record()
+    torch.cuda.synchronize()
+    ms_sample_graph = s.elapsed_time(e)
+    ms_baseline_graph = ms_sample_graph * len(lens) / baseline_sample
     cells = float(lens.sum())
     return {"workload": "batched_shock_tubes_B4096_seed4", "instances": int(len(lens)),
             "total_cells": int(cells), "steps": steps, "ms_batched": ms_batched,
@@ -214,6 +246,9 @@ def bench_batched(steps, baseline_sample=48, use_graph=True):
             "baseline_ms_estimate": ms_baseline, "baseline_sample": baseline_sample,
             "baseline_sample_ms": ms_sample,
             "speedup_vs_one_launch_per_instance": ms_baseline / ms_batched,
+            "baseline_graph_ms_estimate": ms_baseline_graph,
+            "baseline_graph_sample_ms": ms_sample_graph,
+            "speedup_vs_graph_launch_per_instance": ms_baseline_graph / ms_batched,
             "nonfinite_instances": bad_inst}
 
 
@@ -426,6 +461,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--repeats", type=int, default=7,
+                    help="timed repeats of the K steps (median reported; at least 5)")
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--graph", action="store_true", help="replay the steps as a HIP graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -444,9 +481,13 @@ def main():
                     help="skip the 2D characteristic-field figure")
     ap.add_argument("--steps-char2d", type=int, default=100)
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="after the timed region, copy 256 MiB with a plain torch copy "
-                         "(reference kernel for rocprof FETCH_SIZE / WRITE_SIZE scaling)")
+                    help="after the timed region, fill and copy 256 MiB (reference kernels "
+                         "for rocprof FETCH_SIZE / WRITE_SIZE scaling)")
+    ap.add_argument("--traffic-calibration", action="store_true",
+                    help="after the timed region, three times each: fill 256 MiB, sum it, "
+                         "copy it (reference kernels of known traffic for the byte counters)")
     args = ap.parse_args()
+    args.repeats = max(5, args.repeats)
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
@@ -487,18 +528,25 @@ def main():
         u.copy_(torch.tensor(u0, dtype=torch.float64, device=dev))
         torch.cuda.synchronize()
 
-    start = torch.cuda.Event(enable_timing=True)
-    end = torch.cuda.Event(enable_timing=True)
-    log("timed", K, "steps", "(graph)" if graph else "(eager)")
-    torch.cuda.synchronize()
-    start.record(stream)
-    if graph is not None:
-        graph.replay()
-    else:
-        api.rk3_run_1d(u, dx, K, cfl=0.5, prm=prm, stage=stage)
-    end.record(stream)
-    torch.cuda.synchronize()
-    ms = start.elapsed_time(end)
+    # the K timed steps are repeated (each repeat from the initial state, restored outside the
+    # timed region); the median repeat is the reported figure
+    u_init = torch.tensor(u0, dtype=torch.float64, device=dev)
+    reps_ms = []
+    log("timed", K, "steps x", args.repeats, "repeats", "(graph)" if graph else "(eager)")
+    for _ in range(args.repeats):
+        u.copy_(u_init)
+        start = torch.cuda.Event(enable_timing=True)
+        end = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start.record(stream)
+        if graph is not None:
+            graph.replay()
+        else:
+            api.rk3_run_1d(u, dx, K, cfl=0.5, prm=prm, stage=stage)
+        end.record(stream)
+        torch.cuda.synchronize()
+        reps_ms.append(start.elapsed_time(end))
+    ms = float(np.median(reps_ms))
     uf = u.cpu().numpy()
     assert np.isfinite(uf).all() and uf[0].min() > 0, "non-physical state after the run"
 
@@ -511,9 +559,10 @@ def main():
     value = n * 3 * K / (ms * 1e-3)
     nt, kk, lay = autotune.get_row_tuning(3, n)
     autotune.set_row_tuning(0, 0)  # the other workloads use the size-based shapes
-    kname = "row_kernel<%d, %d, EULER1, double, %s>" % (nt, kk, "split" if lay == 1 else "tile")
+    lname = LAYOUT_NAMES[lay]
+    kname = "row_kernel<%d, %d, EULER1, double, %s>" % (nt, kk, lname)
     workload = "euler1d_n%d" % n
-    ktag = "row_kernel_%dx%d_%s" % (nt, kk, "split" if lay == 1 else "tile")
+    ktag = "row_kernel_%dx%d_%s" % (nt, kk, lname)
     traffic = committed_profile("traffic", ktag, workload, "hbm_bytes_per_launch",
                                 ROW_KERNEL_SOURCES)
     valu = committed_profile("valu", ktag, workload, "valu_instr_per_cell", ROW_KERNEL_SOURCES)
@@ -533,10 +582,13 @@ def main():
         "data": "synthetic",
         "config": {"workload": "euler1d_shu_osher_like", "n_cells": n, "nvar": 3,
                    "launch_shape": {"nt": tune_best[0], "k": tune_best[1],
-                                    "layout": "split" if tune_best[2] == 1 else "tile",
+                                    "layout": LAYOUT_NAMES[tune_best[2]],
                                     "autotune_ms_per_step": tune_ms},
                    "bc": "transmissive", "cfl": 0.5, "eps": 1e-40, "A": 10.0,
                    "launch": "hip_graph" if graph else "stream", "kernels_per_step": 3},
+        "timing": {"repeats": len(reps_ms), "statistic": "median",
+                   "ms_per_step_repeats": [r / K for r in reps_ms],
+                   "ms_per_step_min": min(reps_ms) / K, "ms_per_step_max": max(reps_ms) / K},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "kernel": kname, "kernel_ms": kernel_ms},
@@ -550,12 +602,20 @@ def main():
                                              if valu else None)},
         "cpu_baseline": None,
     }
-    if args.copy_calibration:
-        a = torch.ones(32 << 20, dtype=torch.float64, device=dev)  # 256 MiB
+    if args.copy_calibration or args.traffic_calibration:
+        # reference kernels of known traffic for the rocprof byte counters, after the timed
+        # region: a fill (writes 256 MiB), a sum (reads 256 MiB) and a copy (reads and writes
+        # 256 MiB), each kernel run three times
+        a = torch.empty(32 << 20, dtype=torch.float64, device=dev)  # 256 MiB
         b = torch.empty_like(a)
-        b.copy_(a)
+        reps = 3 if args.traffic_calibration else 1
+        for _ in range(reps):
+            a.fill_(1.0)
+            if args.traffic_calibration:
+                a.sum()
+            b.copy_(a)
         torch.cuda.synchronize()
-        rec["copy_calibration_bytes"] = a.numel() * 8
+        rec["calibration_bytes"] = a.numel() * 8
     if not args.no_2d:
         log("2D fp64 and fp32, 4096^2")
         rec["secondary"] = {"euler2d_f64": bench_2d(args.steps_2d, "f64"),

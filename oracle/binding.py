@@ -83,6 +83,7 @@ def lib():
         L.orc_rk3_run_2d_char_f64.argtypes = [i32, i32, i64, i64, p, d, d, d, C.c_int32, p,
                                               C.POINTER(OrcParams), d, p]
         L.orc_num_threads.restype = C.c_int
+        L.orc_set_num_threads.argtypes = [C.c_int]
         _LIB = L
     return _LIB
 
@@ -318,6 +319,11 @@ def rk3_run_1d_char(u, dx, nsteps, cfl=0.5, bc=BC_TRANSMISSIVE, prm=None, gamma=
 
 def num_threads():
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n):
+    """Thread count of the oracle's per-cell loops (results do not depend on it)."""
+    lib().orc_set_num_threads(int(n))
 
 
 def rhs_2d_char(u, dx, dy, bcx=BC_TRANSMISSIVE, bcy=None, alpha8=None, prm=None, gamma=GAMMA):

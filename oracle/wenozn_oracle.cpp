@@ -993,4 +993,14 @@ int orc_num_threads(void) {
 #endif
 }
 
+// Set the thread count of the per-cell loops (results do not depend on it: the only
+// reductions are exact maxima).
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 }  // extern "C"

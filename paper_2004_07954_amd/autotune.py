@@ -81,6 +81,8 @@ def tune_batched(u, offsets, dx, order=None, probe_steps=3, candidates=CANDIDATE
     return api.batch_tuning(nt, k, bpc, lay), timings
 
 
+# (threads per workgroup, cells per thread, layout): layouts 0 (both signs staged) and 1 (one
+# sign at a time)
 ROW_SHAPES = [(256, 4, 0), (256, 2, 0), (256, 1, 0), (128, 4, 0), (128, 8, 0), (64, 8, 0),
               (64, 4, 0), (64, 2, 0), (64, 1, 0), (256, 4, 1), (256, 2, 1), (128, 4, 1), (64, 4, 1)]
 

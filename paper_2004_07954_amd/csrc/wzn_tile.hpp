@@ -249,10 +249,53 @@ __device__ __forceinline__ T row_elem(const RowArgs<T>& a, int c, int g, int n, 
   }
 }
 
+// The states a thread of a tile works on: its K own cells and (threads 0..5) one halo cell.
+template <int K, int NV, typename T>
+struct TileRegs {
+  T U[K][NV];
+  T Uh[NV];
+};
+
+// Issue the loads of a tile's states into registers (the tile whose local cell 0 is cell g0 of
+// the row at element `rowoff` of every component plane).  A persistent kernel issues the next
+// tile's loads before it processes the current tile, so that they are in flight meanwhile.
+template <int NT, int K, int SYS, typename T, bool GHOST = false>
+__device__ __forceinline__ void tile_load(const RowArgs<T>& a, int64_t g0l, int64_t rowoff,
+                                          TileRegs<K, SysInfo<SYS>::NV, T>& r) {
+  constexpr int NV = SysInfo<SYS>::NV;
+  constexpr int TT = NT * K;
+  const int tid = threadIdx.x;
+  const int n = (int)a.n;
+  const int g0 = (int)g0l;
+  const int c0 = g0 + tid * K;
+  const bool full = g0 + TT <= n;
+  // the halo cells -3, -2, -1, T, T+1, T+2 of threads 0..5 first, so that their loads are in
+  // flight together with the own cells'
+  if (tid < 6) {
+    const int hp = tid < 3 ? tid : TT + tid;
+#pragma unroll
+    for (int c = 0; c < NV; ++c) r.Uh[c] = row_elem<GHOST, T>(a, c, g0 + hp - 3, n, rowoff);
+  }
+#pragma unroll
+  for (int c = 0; c < NV; ++c) {
+    const T* up = a.uin + c * a.plane + rowoff;
+    T u[K];
+    if (full) {
+      load_run<K, T>(up + c0, u, ((uintptr_t)(up + g0) & 15) == 0);
+    } else {
+#pragma unroll
+      for (int j = 0; j < K; ++j) u[j] = row_elem<GHOST, T>(a, c, c0 + j, n, rowoff);
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j) r.U[j][c] = u[j];
+  }
+}
+
 template <int NT, int K, int SYS, typename T, bool SPEED, bool SPLIT = false, bool SW = false,
-          int WT = WEIGHTS_ZN, bool GHOST = false>
+          int WT = WEIGHTS_ZN, bool GHOST = false, bool PRE = false>
 __device__ __forceinline__ void row_tile(const RowArgs<T>& a, int64_t g0l, int64_t rowoff,
-                                         T alpha, double dt, T* W, T* EX, double& smax) {
+                                         T alpha, double dt, T* W, T* EX, double& smax,
+                                         const TileRegs<K, SysInfo<SYS>::NV, T>* pre = nullptr) {
   static_assert(!SW || SYS == SYS_EULER2X, "the Steger-Warming split is for the 2D x sweep");
   using TL = Tile<NT, K>;
   constexpr int TT = TL::T;
@@ -282,24 +325,17 @@ __device__ __forceinline__ void row_tile(const RowArgs<T>& a, int64_t g0l, int64
       //      layout, so that the split layout forms w^- from the staged w^+ with the same bits.
       //      The halo cells -3, -2, -1, T, T+1, T+2 of threads 0..5 are loaded first, so that
       //      their loads are in flight together with the own cells'.
+      // (PRE: the caller has issued these loads into *pre, see tile_load)
+      TileRegs<K, NV, T> ld;
+      if constexpr (!PRE) tile_load<NT, K, SYS, T, GHOST>(a, g0l, rowoff, ld);
+      const TileRegs<K, NV, T>& r = PRE ? *pre : ld;
       T Uh[NV];
       const int hp = tid < 3 ? tid : TT + tid;
-      if (tid < 6) {
-#pragma unroll
-        for (int c = 0; c < NV; ++c) Uh[c] = row_elem<GHOST, T>(a, c, g0 + hp - 3, n, rowoff);
-      }
 #pragma unroll
       for (int c = 0; c < NV; ++c) {
-        const T* up = a.uin + c * a.plane + rowoff;
-        T u[K];
-        if (full) {
-          load_run<K, T>(up + c0, u, ((uintptr_t)(up + g0) & 15) == 0);
-        } else {
+        Uh[c] = r.Uh[c];
 #pragma unroll
-          for (int j = 0; j < K; ++j) u[j] = row_elem<GHOST, T>(a, c, c0 + j, n, rowoff);
-        }
-#pragma unroll
-        for (int j = 0; j < K; ++j) Ureg[j][c] = u[j];
+        for (int j = 0; j < K; ++j) Ureg[j][c] = r.U[j][c];
       }
 #pragma unroll
       for (int j = 0; j < K; ++j) {

@@ -11,8 +11,10 @@ The derivative of J along a direction v of rho0 is the central difference
 (J(rho0 + h v) - J(rho0 - h v)) / (2 h) of two runs in __float128 (the oracle's runs with
 the state carried in 113-bit arithmetic), with h far below fp64 resolution, so that the
 weights respond linearly (per-cell perturbations are ~1e-22, the neighbouring differences
-of the data >= ~1e-12) and rounding stays ~1e-12 of the result.  Two step sizes are
-written for the first direction and for the cells as a convergence check.
+of the data >= ~1e-12) and rounding stays ~1e-10 of the result.  Two step sizes a decade
+apart are written for the first direction and for the cells as a convergence check (a step
+of 1e-24 per cell is already rounding-limited: the difference of two 113-bit states then
+carries ~1e-10 relative noise per cell).
 
 Directions: 4 white-noise unit directions (inputs.unit_directions(65536, 4, seed=71)) and
 8 single cells 8192 apart (offset from default_rng(72).integers(0, 8192)).  With the
@@ -67,14 +69,14 @@ def main():
     rows = []
     dirs = I.unit_directions(N, 4, seed=71)
     for k in range(4):
-        for h in ((1e-20, 1e-22) if k == 0 else (1e-20,)):
+        for h in ((1e-20, 1e-19) if k == 0 else (1e-20,)):
             print("direction %d, h = %g" % (k, h), flush=True)
             rows.append(("direction", k, h, float(np.sum(pair(dirs[k], h)))))
     off = int(np.random.default_rng(72).integers(0, 8192))
     cells = off + 8192 * np.arange(8)
     e = np.zeros(N)
     e[cells] = 1.0
-    for h in (1e-22, 1e-24):
+    for h in (1e-22, 1e-21):
         print("cells, h = %g" % h, flush=True)
         contrib = pair(e, h)
         for c in cells:
