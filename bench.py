@@ -37,6 +37,10 @@ CHAR_KERNEL_SOURCES = ("wzn_char.hip", "wzn_rows.hpp", "wzn_tile.hpp", "wzn_devi
                        "wzn_host.hpp")
 EULER2D_KERNEL_SOURCES = ("wzn_2d.hip", "wzn_rows.hip", "wzn_rows.hpp", "wzn_tile.hpp",
                           "wzn_device.hpp", "wzn_host.hpp")
+CHAR2D_KERNEL_SOURCES = ("wzn_char2d.hip", "wzn_rows.hpp", "wzn_tile.hpp", "wzn_device.hpp",
+                         "wzn_host.hpp")
+VJP_KERNEL_SOURCES = ("wzn_vjp.hip", "wzn_rows.hpp", "wzn_tile.hpp", "wzn_device.hpp",
+                      "wzn_host.hpp")
 
 
 def kernel_source_hash(files):
@@ -148,23 +152,32 @@ def bench_2d(steps, dtype_name, warmup=3, split="lf"):
            "steps": steps, "ms_per_step": ms / steps,
            "value": nx * ny * 3 * steps / (ms * 1e-3), "unit": "cell-RHS/s",
            "stage_ms": stage_ms, "hbm_gbs_algorithmic": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}
-    if dtype_name == "f64":
-        # fp64 VALU side: the x sweep plus the column kernel per stage, from the committed
-        # counter profile of the 2D kernels (Steger-Warming steps run the column kernel with
-        # the wave-speed epilogue in their last stage only)
-        v = committed_profile("counters", "euler2d", "kernels", "valu_per_cell",
-                              EULER2D_KERNEL_SOURCES)
-        per_cell = None
-        if v and split == "lf":
-            per_cell = v.get("x_lf_f64", 0) + v.get("col_lf_f64_speed", 0)
-        elif v:
-            per_cell = v.get("x_sw_f64", 0) + (2 * v.get("col_sw_f64", 0) +
-                                               v.get("col_sw_f64_speed", 0)) / 3.0
-        ach = per_cell * nx * ny / (stage_ms * 1e-3) if per_cell else None
-        rec["roofline_alu"] = {"bound": "alu", "unit": "VALU lane-instr/s",
-                               "valu_instr_per_cell_stage": per_cell, "achieved": ach,
-                               "peak": VALU_LANE_PEAK,
-                               "frac": ach / VALU_LANE_PEAK if ach else None}
+    # VALU and measured-traffic side: the x sweep plus the column kernel per stage, from the
+    # committed counter profile of the 2D kernels (Steger-Warming steps run the column kernel
+    # with the wave-speed epilogue in their last stage only)
+    sfx = "_" + dtype_name
+    per_cell = meas = None
+    v = committed_profile("counters", "euler2d", "kernels", "valu_per_cell",
+                          EULER2D_KERNEL_SOURCES)
+    hb = committed_profile("counters", "euler2d", "kernels", "hbm_bytes_per_cell",
+                           EULER2D_KERNEL_SOURCES)
+
+    def stage_mean(d):
+        if split == "lf":
+            return d["x_lf" + sfx] + d["col_lf" + sfx + "_speed"]
+        return d["x_sw" + sfx] + (2 * d["col_sw" + sfx] + d["col_sw" + sfx + "_speed"]) / 3.0
+    if v:
+        per_cell = stage_mean(v)
+    if hb:
+        meas = stage_mean(hb)
+    ach = per_cell * nx * ny / (stage_ms * 1e-3) if per_cell else None
+    # fp32 instructions issue at the fp32 rate; the lane-instruction peak is the same
+    # (one instruction per lane per cycle), so one figure serves both
+    rec["roofline_alu"] = {"bound": "alu", "unit": "VALU lane-instr/s",
+                           "valu_instr_per_cell_stage": per_cell, "achieved": ach,
+                           "peak": VALU_LANE_PEAK,
+                           "frac": ach / VALU_LANE_PEAK if ach else None}
+    rec["hbm_bytes_per_cell_stage_measured"] = meas
     return rec
 
 
@@ -326,10 +339,28 @@ def bench_char2d(steps, warmup=3):
     torch.cuda.synchronize()
     ms = s.elapsed_time(e)
     assert torch.isfinite(u).all().item()
-    return {"workload": "euler2d_riemann_case2_characteristic_%dx%d" % (nx, ny), "dtype": "f64",
-            "steps": steps, "ms_per_step": ms / steps,
-            "value": nx * ny * 3 * steps / (ms * 1e-3), "unit": "cell-RHS/s",
-            "stage_ms": ms / (3 * steps)}
+    stage_ms = ms / (3 * steps)
+    # algorithmic bytes per cell and stage: two transposes (read + write one state each), the y
+    # sweep (read the transposed state, write its part of L), the fused x sweep (read U and the
+    # y part, U^n in stages 2 and 3, write the stage output)
+    alg = 4 * 8 * (2 + 2 + 2 + (2 + 3 + 3) / 3.0 + 1)
+    rec = {"workload": "euler2d_riemann_case2_characteristic_%dx%d" % (nx, ny), "dtype": "f64",
+           "steps": steps, "ms_per_step": ms / steps,
+           "value": nx * ny * 3 * steps / (ms * 1e-3), "unit": "cell-RHS/s",
+           "stage_ms": stage_ms,
+           "hbm_gbs_algorithmic": alg * nx * ny / (stage_ms * 1e-3) / 1e9,
+           "hbm_bytes_per_cell_stage_algorithmic": alg}
+    rec["hbm_frac"] = rec["hbm_gbs_algorithmic"] / HBM_PEAK_GBS
+    c = committed_profile("counters", "char2d", "kernels_riemann2_2400", "stage_valu_per_cell",
+                          CHAR2D_KERNEL_SOURCES)
+    b = committed_profile("counters", "char2d", "kernels_riemann2_2400",
+                          "stage_hbm_bytes_per_cell", CHAR2D_KERNEL_SOURCES)
+    ach = c * nx * ny / (stage_ms * 1e-3) if c else None
+    rec["roofline_alu"] = {"bound": "alu", "unit": "VALU lane-instr/s",
+                           "valu_instr_per_cell_stage": c, "achieved": ach,
+                           "peak": VALU_LANE_PEAK, "frac": ach / VALU_LANE_PEAK if ach else None}
+    rec["hbm_bytes_per_cell_stage_measured"] = b
+    return rec
 
 
 def bench_strip(evals=100):
