@@ -10,11 +10,12 @@ state of the same case.
 The derivative of J along a direction v of rho0 is the central difference
 (J(rho0 + h v) - J(rho0 - h v)) / (2 h) of two runs in __float128 (the oracle's runs with
 the state carried in 113-bit arithmetic), with h far below fp64 resolution, so that the
-weights respond linearly (per-cell perturbations are ~1e-22, the neighbouring differences
-of the data >= ~1e-12) and rounding stays ~1e-10 of the result.  Two step sizes a decade
-apart are written for the first direction and for the cells as a convergence check (a step
-of 1e-24 per cell is already rounding-limited: the difference of two 113-bit states then
-carries ~1e-10 relative noise per cell).
+weights respond linearly (per-cell perturbations are ~1e-21, the neighbouring differences
+of the data >= ~1e-12).  The truncation error of such steps is negligible; what limits the
+quotient is the runs' rounding, which grows as 1/h.  Two step sizes a decade apart are
+written for the first direction (1e-20, 1e-19: they agree to ~4e-12) and for the cells
+(1e-22, 1e-21: they agree to ~1e-8, the rounding noise of the smaller step; a step of
+1e-24 per cell was noisier still, ~1e-7).  The larger step is the reference.
 
 Directions: 4 white-noise unit directions (inputs.unit_directions(65536, 4, seed=71)) and
 8 single cells 8192 apart (offset from default_rng(72).integers(0, 8192)).  With the
