@@ -319,8 +319,8 @@ def bench_char(n, steps, warmup=3, cpu_steps=3):
 def bench_char2d(steps, warmup=3):
     """Secondary figure: 2D Euler with each sweep's reconstruction in local characteristic
     fields (the 1D procedure of Sec. 4.3 along x and y), on the paper's second Riemann case at
-    2400^2, transmissive, CFL 0.5, fp64.  One stage = the x sweep, two transposes, the y sweep
-    of the transposed state and the finish kernel."""
+    2400^2, transmissive, CFL 0.5, fp64.  One stage = the column kernel (the y sweep) and the
+    x sweep with the stage epilogue."""
     import torch
     from paper_2004_07954_amd import api, inputs as I
     nx = ny = 2400
@@ -328,7 +328,7 @@ def bench_char2d(steps, warmup=3):
     u0t = torch.tensor(u0, dtype=torch.float64, device="cuda")
     u = u0t.clone()
     stage = torch.empty((2, 4, ny, nx), dtype=torch.float64, device="cuda")
-    work = torch.empty(12 * nx * ny, dtype=torch.float64, device="cuda")
+    work = torch.empty(4 * nx * ny, dtype=torch.float64, device="cuda")
     api.rk3_run_2d_char(u, dx, dy, warmup, stage=stage, work=work)
     u.copy_(u0t)
     torch.cuda.synchronize()
@@ -340,10 +340,9 @@ def bench_char2d(steps, warmup=3):
     ms = s.elapsed_time(e)
     assert torch.isfinite(u).all().item()
     stage_ms = ms / (3 * steps)
-    # algorithmic bytes per cell and stage: two transposes (read + write one state each), the y
-    # sweep (read the transposed state, write its part of L), the fused x sweep (read U and the
-    # y part, U^n in stages 2 and 3, write the stage output)
-    alg = 4 * 8 * (2 + 2 + 2 + (2 + 3 + 3) / 3.0 + 1)
+    # algorithmic bytes per cell and stage: the y sweep (read U, write its part of L), the
+    # fused x sweep (read U and the y part, U^n in stages 2 and 3, write the stage output)
+    alg = 4 * 8 * (2 + (2 + 3 + 3) / 3.0 + 1)
     rec = {"workload": "euler2d_riemann_case2_characteristic_%dx%d" % (nx, ny), "dtype": "f64",
            "steps": steps, "ms_per_step": ms / steps,
            "value": nx * ny * 3 * steps / (ms * 1e-3), "unit": "cell-RHS/s",

@@ -288,9 +288,8 @@ int32_t wzn_rk3_step_2d(const wzn_params* p, void* u, void* stage, int64_t nx, i
  * right eigenvectors.  fp64 only, p->flux_split must be WZN_SPLIT_LF and p->weights
  * WZN_WEIGHTS_ZN (else WZN_ERR_DTYPE / WZN_ERR_UNSUPPORTED).
  *
- * work: device scratch of wzn_char2d_work_doubles(nx, ny) doubles (three states: the y part
- * of L, the state transposed with its two momenta exchanged, and that state's x-sweep part),
- * distinct from the other arrays. */
+ * work: device scratch of wzn_char2d_work_doubles(nx, ny) doubles (one state: the y part of
+ * L), distinct from the other arrays. */
 int64_t wzn_char2d_work_doubles(int64_t nx, int64_t ny);
 
 /* wzn_rhs_2d_char: dudt = L(u) for u[4][ny][nx].  alpha8: NULL (reduced from u, or the
@@ -303,7 +302,7 @@ int32_t wzn_rhs_2d_char(const wzn_params* p, const void* u, void* dudt, void* wo
 /* wzn_rk3_run_2d_char: advance u[4][ny][nx] in place by `nsteps` TVD-RK3 steps of the
  * characteristic scheme; stage: device scratch of 2 * 4 * nx * ny doubles; dt as in
  * wzn_rk3_run_2d (dt_in / dt_out as there).  The alphas are reduced from every stage input
- * (p->lf_alpha_x and p->lf_alpha_y must be < 0).  Enqueued as 2 + 12 * nsteps kernels with
+ * (p->lf_alpha_x and p->lf_alpha_y must be < 0).  Enqueued as 2 + 6 * nsteps kernels with
  * no host synchronisation. */
 int32_t wzn_rk3_run_2d_char(const wzn_params* p, void* u, void* stage, void* work, int64_t nx,
                             int64_t ny, double dx, double dy, double cfl, int32_t nsteps,

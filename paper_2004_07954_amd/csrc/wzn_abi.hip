@@ -402,7 +402,7 @@ int32_t wzn_rk3_run_2d(const wzn_params* p, void* u, void* stage, int64_t nx, in
 }
 
 int64_t wzn_char2d_work_doubles(int64_t nx, int64_t ny) {
-  return nx > 0 && ny > 0 ? 12 * nx * ny : 0;
+  return nx > 0 && ny > 0 ? 4 * nx * ny : 0;
 }
 
 static int check_char2d(const wzn_params* p, int64_t nx, int64_t ny, double dx, double dy,

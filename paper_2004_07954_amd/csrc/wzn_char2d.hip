@@ -12,13 +12,13 @@
 // |u|, |u|, |u + c| over the cells of the RHS input; ghat_k = WZN(w^+_k) + WZN(w^-_k mirrored)
 // and the interface flux is R ghat / 2.
 //
-// The y sweep is the same kernel on the transposed state with the two momenta exchanged:
-// the y Jacobian of U is the x Jacobian of the exchanged state, and the exchange flips only
-// the sign of the shear eigenvector, which cancels in R ghat because the reconstruction is an
-// odd function of its data.  One right-hand side is: transpose U -> Ut; x sweep of Ut -> Lyt;
-// transpose Lyt -> Ly; then the x sweep of U, whose epilogue adds Ly and writes L, or the
-// TVD-RK3 stage combination (U from LDS) with the per-field maxima of the output for the next
-// stage's alphas and the next step's dt.
+// The y sweep is the same procedure on the state with the two momenta exchanged: the y
+// Jacobian of U is the x Jacobian of the exchanged state, and the exchange flips only the sign
+// of the shear eigenvector, which cancels in R ghat because the reconstruction is an odd
+// function of its data.  A column kernel evaluates it in place, walking the columns of U (no
+// transposed copy).  One right-hand side is: the column kernel -> Ly; then the x sweep of U,
+// whose epilogue adds Ly and writes L, or the TVD-RK3 stage combination (U from LDS) with the
+// per-field maxima of the output for the next stage's alphas and the next step's dt.
 #include <hip/hip_runtime.h>
 
 #include "wzn_device.hpp"
@@ -61,15 +61,123 @@ struct Char2Args {
 // staged per-cell planes
 enum { C2_U0 = 0, C2_F0 = 4, C2_S = 8, C2_VU = 9, C2_VV = 10, C2_H = 11, C2_N = 12 };
 constexpr int C2_NT = 256;
+// column kernel (the y sweep): CY_TX columns x CY_TY interfaces per workgroup
+constexpr int CY_TX = 16, CY_TY = 16;
 
-// One workgroup: NT interfaces of one row (NT - 1 output cells; neighbouring tiles overlap by
-// one interface).  Every cell of the tile and its halo is loaded once and its U, F, sqrt(rho),
-// u, v and H are staged in LDS; each thread builds the Roe eigen-system of its interface and
-// reconstructs the four fields one after another, re-reading the stencil from LDS for each.
 __device__ __forceinline__ void char2_speeds(double rho, double mx, double my, double E,
                                              double gamma, double (&s)[6]);
 __device__ __forceinline__ void block_max6(double (&s)[6], unsigned long long* slot);
 
+// The sweep's alphas for the four fields (Sec. 4.3: one per field, |un - c|, |un|, |un|,
+// |un + c|) from three slots, a device array of four or one constant.
+__device__ __forceinline__ void char2_alphas(const Char2Args& a, double (&al)[4]) {
+  if (a.alpha_slot) {
+    al[0] = slot_value(a.alpha_slot);
+    al[1] = al[2] = slot_value(a.alpha_slot + 1);
+    al[3] = slot_value(a.alpha_slot + 2);
+  } else if (a.alpha_arr) {
+#pragma unroll
+    for (int f = 0; f < 4; ++f) al[f] = a.alpha_arr[f];
+  } else {
+#pragma unroll
+    for (int f = 0; f < 4; ++f) al[f] = a.alpha_const;
+  }
+}
+
+// Stage one cell of a sweep at LDS position l (planes PS elements apart): U, the flux along
+// the sweep F = (mn, mn un + p, mn ut, un (E + p)), sqrt(rho), un, ut and H = (E + p) / rho,
+// where mn / mt are the normal / tangential momenta (mx / my in the x sweep, my / mx in the
+// y sweep, which is how the y sweep becomes the x procedure of the exchanged state).
+template <int PS>
+__device__ __forceinline__ void char2_stage(double* S, int l, double rho, double mn, double mt,
+                                            double E, double gm1) {
+  const double r = rcp_nr(rho);
+  const double u = mn * r, v = mt * r;
+  const double p = gm1 * fma_t(-(0.5 * mt), v, fma_t(-(0.5 * mn), u, E));
+  S[C2_U0 * PS + l] = rho;
+  S[(C2_U0 + 1) * PS + l] = mn;
+  S[(C2_U0 + 2) * PS + l] = mt;
+  S[(C2_U0 + 3) * PS + l] = E;
+  S[C2_F0 * PS + l] = mn;
+  S[(C2_F0 + 1) * PS + l] = fma_t(mn, u, p);
+  S[(C2_F0 + 2) * PS + l] = mn * v;
+  S[(C2_F0 + 3) * PS + l] = u * (E + p);
+  S[C2_S * PS + l] = sqrt_gs(rho);
+  S[C2_VU * PS + l] = u;
+  S[C2_VV * PS + l] = v;
+  S[C2_H * PS + l] = (E + p) * r;
+}
+
+// Twice the interface flux R ghat (normal-first component order) of the interface between
+// stencil cells 2 and 3, the six cells at LDS positions t, t + ES, ..., t + 5 ES.
+template <int PS, int ES>
+__device__ __forceinline__ void char2_face(const double* S, int t, const double (&al)[4],
+                                           double gm1, double eps_s, double Aq,
+                                           double (&fh)[4]) {
+#define SV(pl, j) S[(pl) * PS + t + (j) * ES]
+  const double sL = SV(C2_S, 2), sR = SV(C2_S, 3);
+  const double wl = sL * rcp_nr(sL + sR);
+  const double uh = fma_t(wl, SV(C2_VU, 2) - SV(C2_VU, 3), SV(C2_VU, 3));
+  const double vh = fma_t(wl, SV(C2_VV, 2) - SV(C2_VV, 3), SV(C2_VV, 3));
+  const double Hh = fma_t(wl, SV(C2_H, 2) - SV(C2_H, 3), SV(C2_H, 3));
+  const double q2 = fma_t(uh, uh, vh * vh);
+  const double c = sqrt_gs(gm1 * fma_t(-0.5, q2, Hh));
+  const double ic = rcp_nr(c);
+  const double b1 = (gm1 * ic) * ic;
+  const double b1u = b1 * uh, b1v = b1 * vh;
+  const double b2 = (0.5 * b1) * q2;
+  const double uic = uh * ic;
+  // rows 0, 1, 3 of Lc (row 2, the shear field, is (-v, 0, 1, 0))
+  const double Lc[4][4] = {{0.5 * (b2 + uic), -0.5 * (b1u + ic), -0.5 * b1v, 0.5 * b1},
+                           {1.0 - b2, b1u, b1v, -b1},
+                           {0.0, 0.0, 0.0, 0.0},
+                           {0.5 * (b2 - uic), -0.5 * (b1u - ic), -0.5 * b1v, 0.5 * b1}};
+  double gh[4];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    // a compiler memory barrier: the stencil is read again from LDS for every field
+    if (f > 0) asm volatile("" ::: "memory");
+    double wp[5], wm[5];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      double V, G;
+      if (f == 2) {
+        V = fma_t(-vh, SV(C2_U0, j), SV(C2_U0 + 2, j));
+        G = fma_t(-vh, SV(C2_F0, j), SV(C2_F0 + 2, j));
+      } else {
+        V = fma_t(Lc[f][3], SV(C2_U0 + 3, j),
+                  fma_t(Lc[f][2], SV(C2_U0 + 2, j),
+                        fma_t(Lc[f][1], SV(C2_U0 + 1, j), Lc[f][0] * SV(C2_U0, j))));
+        G = fma_t(Lc[f][3], SV(C2_F0 + 3, j),
+                  fma_t(Lc[f][2], SV(C2_F0 + 2, j),
+                        fma_t(Lc[f][1], SV(C2_F0 + 1, j), Lc[f][0] * SV(C2_F0, j))));
+      }
+      if (j < 5) wp[j] = fma_t(al[f], V, G);
+      if (j > 0) wm[5 - j] = fma_t(-al[f], V, G);
+    }
+    double hp, hm;
+    wzn_window<1>(wp, &hp, eps_s, Aq);
+    wzn_window<1>(wm, &hm, eps_s, Aq);
+    gh[f] = hp + hm;
+    // materialise here: otherwise every field's arithmetic is sunk below the last field's
+    // loads and all four fields' stencils are live at once (twice the registers)
+    asm volatile("" : "+v"(gh[f]));
+  }
+#undef SV
+  const double uc = uh * c;
+  fh[0] = (gh[0] + gh[1]) + gh[3];
+  fh[1] = fma_t(uh - c, gh[0], fma_t(uh, gh[1], (uh + c) * gh[3]));
+  fh[2] = fma_t(vh, gh[0] + gh[1] + gh[3], gh[2]);
+  fh[3] = fma_t(Hh - uc, gh[0], fma_t(0.5 * q2, gh[1], fma_t(vh, gh[2], (Hh + uc) * gh[3])));
+}
+
+// The x sweep.  One workgroup: NT interfaces of one row (NT - 1 output cells; neighbouring
+// tiles overlap by one interface).  Every cell of the tile and its halo is loaded once and its
+// U, F, sqrt(rho), u, v and H are staged in LDS; each thread builds the Roe eigen-system of its
+// interface and reconstructs the four fields one after another, re-reading the stencil from
+// LDS for each.  FUSE: the epilogue adds the y part and forms L or the stage output.  (The
+// same face as char2_face, written out: with the helper the compiler keeps ten more registers
+// live here and the fused kernel drops from four waves per SIMD to three.)
 template <int NT, bool FUSE>
 __global__ __launch_bounds__(NT) void char2_kernel(Char2Args a) {
   constexpr int NC = NT + 5;  // cells c0 - 3 .. c0 + NT + 1
@@ -246,26 +354,58 @@ __global__ __launch_bounds__(NT) void char2_kernel(Char2Args a) {
   }
 }
 
-// dst[v'][c][r] = src[v][r][c] for src [4][R][C]: the transpose with the two momenta exchanged
-// (v' = 0, 2, 1, 3).  64 x 64 tiles staged in LDS (one component per workgroup row of the grid).
-__global__ __launch_bounds__(256) void transpose_swap_kernel(const double* __restrict__ src,
-                                                             double* __restrict__ dst, int64_t R,
-                                                             int64_t C, int64_t tiles_c) {
-  __shared__ double tile[64][65];
-  const int v = blockIdx.y;
-  const int vd = v == 1 ? 2 : (v == 2 ? 1 : v);
-  const int64_t P = R * C;
-  const int64_t tr = (int64_t)blockIdx.x / tiles_c, tc = (int64_t)blockIdx.x - tr * tiles_c;
-  const int64_t r0 = tr * 64, c0 = tc * 64;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  for (int i = ty; i < 64; i += 4) {
-    const int64_t r = r0 + i, c = c0 + tx;
-    if (r < R && c < C) tile[i][tx] = src[v * P + r * C + c];
+// The y sweep, walking the columns of the untransposed state u[4][ny][nx] (a.n = ny cells per
+// column, a.rows = nx columns, a.tiles = tiles per column).  One workgroup: TX consecutive
+// columns x TY interfaces of each (TY - 1 output cells; tiles overlap by one interface along
+// y).  The tile's cells and its 3 + 2 halo rows are staged once, row segments of TX cells
+// loaded together; thread (column x, interface t) evaluates the same face as the x sweep of
+// the exchanged state (my as the normal momentum), and writes its part of L with the momenta
+// back in place.
+template <int TX, int TY>
+__global__ __launch_bounds__(TX * TY) void char2_col_kernel(Char2Args a) {
+  constexpr int NR = TY + 5;     // rows y0 - 3 .. y0 + TY + 1
+  constexpr int PS = NR * TX;    // elements per staged plane
+  __shared__ double S[C2_N * PS];
+  __shared__ double FH[4][TY * TX];
+  const int tid = threadIdx.x;
+  const int64_t nx = a.rows;
+  const int64_t cblk = (int64_t)blockIdx.x / a.tiles;
+  const int tile = (int)((int64_t)blockIdx.x - cblk * a.tiles);
+  const int64_t x0 = cblk * TX;
+
+  double al[4];
+  char2_alphas(a, al);
+  if (blockIdx.x == 0 && a.slot_zero && tid < a.zero_count) a.slot_zero[tid] = 0ull;
+
+  const int y0 = tile * (TY - 1);
+  const double gm1 = a.gamma - 1.0;
+  for (int l = tid; l < PS; l += TX * TY) {
+    const int r = l / TX, cx = l - r * TX;
+    const int64_t x = x0 + cx < nx ? x0 + cx : nx - 1;  // columns past the grid: any cell
+    const int64_t ci = (int64_t)bc_cell(y0 - 3 + r, a.n, a.bc) * nx + x;
+    char2_stage<PS>(S, l, a.uin[ci], a.uin[2 * a.plane + ci], a.uin[a.plane + ci],
+                    a.uin[3 * a.plane + ci], gm1);
   }
   __syncthreads();
-  for (int i = ty; i < 64; i += 4) {
-    const int64_t c = c0 + i, r = r0 + tx;
-    if (c < C && r < R) dst[vd * P + c * R + r] = tile[tx][i];
+
+  const int cx = tid % TX, t = tid / TX;
+  {
+    double fh[4];
+    char2_face<PS, TX>(S, t * TX + cx, al, gm1, a.eps_s, a.Aq, fh);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) FH[v][tid] = fh[v];
+  }
+  __syncthreads();
+
+  const int64_t x = x0 + cx;
+  const int y = y0 + t;
+  if (t < TY - 1 && y < a.n && x < nx) {
+    double* out = a.out + (int64_t)y * nx + x;
+    // normal-first order back to (rho, mx, my, E): the y sweep's normal momentum is my
+    out[0] = (FH[0][tid] - FH[0][tid + TX]) * a.half_inv_h;
+    out[2 * a.plane] = (FH[1][tid] - FH[1][tid + TX]) * a.half_inv_h;
+    out[a.plane] = (FH[2][tid] - FH[2][tid + TX]) * a.half_inv_h;
+    out[3 * a.plane] = (FH[3][tid] - FH[3][tid + TX]) * a.half_inv_h;
   }
 }
 
@@ -324,13 +464,13 @@ static int launch_char2(Char2Args a, hipStream_t s) {
   return check_launch("char2_kernel");
 }
 
-static int launch_transpose_swap(const double* src, double* dst, int64_t R, int64_t C,
-                                 hipStream_t s) {
-  const int64_t tc = (C + 63) / 64, tr = (R + 63) / 64;
-  if (tc * tr > 0x7fffffff) return set_error(WZN_ERR_SIZE, "grid too large (transpose)");
-  hipLaunchKernelGGL(transpose_swap_kernel, dim3((unsigned)(tc * tr), 4), dim3(256), 0, s, src,
-                     dst, R, C, tc);
-  return check_launch("transpose_swap_kernel");
+static int launch_char2_col(Char2Args a, hipStream_t s) {
+  a.tiles = ((int64_t)a.n + CY_TY - 2) / (CY_TY - 1);
+  const int64_t blocks = a.tiles * ((a.rows + CY_TX - 1) / CY_TX);
+  if (blocks > 0x7fffffff) return set_error(WZN_ERR_SIZE, "grid too large (characteristic sweep)");
+  hipLaunchKernelGGL((char2_col_kernel<CY_TX, CY_TY>), dim3((unsigned)blocks), dim3(CY_TX * CY_TY),
+                     0, s, a);
+  return check_launch("char2_col_kernel");
 }
 
 static int launch_char2_speed(const double* u, int64_t N, double gamma,
@@ -366,29 +506,20 @@ static void set_alpha(Char2Args& a, const wzn_params* p, const Char2Alpha& al, i
   else a.alpha_const = dir == 0 ? p->lf_alpha_x : p->lf_alpha_y;
 }
 
-// The y part of L(U) over the untransposed grid, into work[0 .. 4 nx ny): work holds three
-// states, [0] the y part, [1] the transposed state, [2] its x-sweep part.  The y sweep's
-// workgroup 0 clears the six words zero6 (if given).
+// The y part of L(U) into work[0 .. 4 nx ny), by the column kernel.  Its workgroup 0 clears
+// the six words zero6 (if given).
 static int char2_ypart(const wzn_params* p, const double* u, double* work, int64_t nx,
                        int64_t ny, double dy, const Char2Alpha& al, unsigned long long* zero6,
                        hipStream_t s) {
-  const int64_t M = 4 * nx * ny;
-  double* Ly = work;
-  double* Ut = work + M;
-  double* Lyt = work + 2 * M;
-  int st = launch_transpose_swap(u, Ut, ny, nx, s);
-  if (st) return st;
   Char2Args ay = char2_base(p, ny, nx, dy, p->bc_y);
-  ay.uin = Ut;
-  ay.out = Lyt;
+  ay.uin = u;
+  ay.out = work;
   set_alpha(ay, p, al, 1);
   if (zero6) {
     ay.slot_zero = zero6;
     ay.zero_count = 6;
   }
-  st = launch_char2<false>(ay, s);
-  if (st) return st;
-  return launch_transpose_swap(Lyt, Ly, nx, ny, s);
+  return launch_char2_col(ay, s);
 }
 
 int rhs_2d_char(const wzn_params* p, const double* u, double* dudt, double* work, int64_t nx,
