@@ -160,6 +160,17 @@ int32_t wzn_reconstruct(const wzn_params* p, const double* f, double* fhat, int6
 int32_t wzn_rhs_1d(const wzn_params* p, const void* u, void* dudt, int64_t n, double dx,
                    void* ws, void* stream);
 
+/* wzn_rhs_1d_noalloc: wzn_rhs_1d without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, results (bit for bit) and errors as wzn_rhs_1d; the library's
+ * own scratch (the alpha reduction slot and the debug-scan words, 4 KiB whatever n) lives in a
+ * static device array, one per GPU, held until the process ends.  Nothing is allocated.  All
+ * calls on one GPU share that array: calls that overlap on one GPU (other streams or host
+ * threads) race on it and must be serialised by the caller.  Sizes as wzn_rhs_1d (n <= 2^30);
+ * WZN_ERR_HIP if the array's device address cannot be taken. */
+int32_t wzn_rhs_1d_noalloc(const wzn_params* p, const void* u, void* dudt, int64_t n, double dx,
+                           void* stream);
+
 /* One GPU's share of a slab decomposition of a 1D Euler row.
  * wzn_speed_max_1d: *speed1 = max over the cells of u [3][n] of |u| + c (device double): the
  *   per-shard maximum that an all-reduce (MAX) turns into the global Lax-Friedrichs alpha

@@ -49,6 +49,7 @@ SIGNATURES = [
     ("wzn_workspace_bytes", _SZ, [_PP, _I64, _I64]),
     ("wzn_reconstruct", _I32, [_PP, _P, _P, _I64, _P]),
     ("wzn_rhs_1d", _I32, [_PP, _P, _P, _I64, _D, _P, _P]),
+    ("wzn_rhs_1d_noalloc", _I32, [_PP, _P, _P, _I64, _D, _P]),
     ("wzn_speed_max_1d", _I32, [_PP, _P, _I64, _P, _P, _P]),
     ("wzn_rhs_1d_slab", _I32, [_PP, _P, _P, _P, _P, _I64, _D, _P, _P, _P]),
     ("wzn_rk3_run_1d", _I32, [_PP, _P, _P, _I64, _D, _D, _I32, _P, _P, _P, _P, _P, _P]),
