@@ -1,9 +1,9 @@
 """2D Euler with each sweep's reconstruction in local characteristic fields on the GPU
 (wzn_rhs_2d_char, wzn_rk3_run_2d_char) against the oracle: right-hand sides at ragged sizes
 with both boundary conditions and on the paper's Riemann data, frozen alphas, runs with their
-dt history, the x/y exchange (bit for bit: the y sweep is the x sweep of the transposed
-state), the reduction to the 1D characteristic scheme, conservation and the argument
-checks."""
+dt history, the x/y exchange (bit for bit: the column kernel's y sweep evaluates the x
+sweep's faces on the state with its momenta exchanged), the reduction to the 1D
+characteristic scheme, conservation and the argument checks."""
 import numpy as np
 import pytest
 
