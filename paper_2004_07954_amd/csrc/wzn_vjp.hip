@@ -155,11 +155,15 @@ __device__ __forceinline__ int64_t map_cell(int64_t p, int64_t n, int bc) {
 // latency-bound at the adjoint workload's size).  Every global load is issued at kernel start:
 // the states of the cells the stencils read (g0 - 5 .. g0 + VJP_NI - 1), the cotangents mu of
 // g0 - 3 .. g0 + VJP_NI - 3, and the accumulator of the output cells.
-constexpr int VJP_NI = 64;
+// 72 interfaces (432 threads, 67 output cells) with at most 72 VGPRs (7 waves per SIMD, 20 B
+// of spills): four workgroups per CU, so the adjoint workload's 979 workgroups run in one
+// round; 64 interfaces at 76 VGPRs took 1111 workgroups in two (backward pass 2 % slower).
+constexpr int VJP_NI = 72;
 constexpr int VJP_NT = 6 * VJP_NI;
 constexpr int VJP_TC = VJP_NI - 5;  // output cells per workgroup
 
-__global__ __launch_bounds__(VJP_NT) void vjp_kernel(VjpArgs a) {
+__global__ __launch_bounds__(VJP_NT) __attribute__((amdgpu_waves_per_eu(7)))
+void vjp_kernel(VjpArgs a) {
   constexpr int NI = VJP_NI, TC = VJP_TC;
   constexpr int NW = NI + 5;  // staged cells g0 - 5 .. g0 + NI - 1
   constexpr int NM = NI + 1;  // staged cotangents g0 - 3 .. g0 + NI - 3
