@@ -242,11 +242,36 @@ __device__ __forceinline__ double slot_value(const unsigned long long* slot) {
   return __longlong_as_double((long long)(*slot));
 }
 
-// Wave-wide max (64 lanes) via cross-lane shuffles.
+// v of another lane by a DPP lane move of both 32-bit halves (CTRL, ROW_MASK as in the DPP
+// encoding; lanes of rows outside ROW_MASK keep their own v).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = (int)b, hi = (int)(b >> 32);
+  const int lo2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROW_MASK, 0xF, false);
+  const int hi2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROW_MASK, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi2 << 32) |
+                                          (unsigned)lo2));
+}
+
+// Wave-wide max of 64 active lanes, returned in every lane: DPP lane moves (exchange within
+// quads, row half-mirror, row mirror: every lane of a row holds the row's max; then the row
+// broadcasts of lane 15 to rows 1 and 3 and of lane 31 to rows 2 and 3), read back from lane
+// 63.  VALU lane moves instead of the LDS crossbar of shuffles (ds_bpermute): six dependent
+// steps of a few cycles rather than of an LDS round trip.  max is exact and its order does
+// not matter, so every result is the same bits as a shuffle tree's.
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-  return v;
+  v = fmax(v, dpp_move<0xB1, 0xF>(v));   // quad_perm [1, 0, 3, 2]
+  v = fmax(v, dpp_move<0x4E, 0xF>(v));   // quad_perm [2, 3, 0, 1]
+  v = fmax(v, dpp_move<0x141, 0xF>(v));  // row_half_mirror
+  v = fmax(v, dpp_move<0x140, 0xF>(v));  // row_mirror
+  v = fmax(v, dpp_move<0x142, 0xA>(v));  // row_bcast:15
+  v = fmax(v, dpp_move<0x143, 0xC>(v));  // row_bcast:31
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                          (unsigned)lo));
 }
 
 }  // namespace wzn
