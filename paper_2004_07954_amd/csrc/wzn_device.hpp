@@ -254,6 +254,14 @@ __device__ __forceinline__ double dpp_move(double v) {
                                           (unsigned)lo2));
 }
 
+// The value of lane i - 1 in lane i (lane 0 keeps its own): one DPP wave_shr:1 lane move per
+// 32-bit half, in place of a shuffle through the LDS crossbar.  All 64 lanes must be active.
+__device__ __forceinline__ double lane_prev(double v) { return dpp_move<0x138, 0xF>(v); }
+__device__ __forceinline__ float lane_prev(float v) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x138, 0xF, 0xF, false));
+}
+
 // Wave-wide max of 64 active lanes, returned in every lane: DPP lane moves (exchange within
 // quads, row half-mirror, row mirror: every lane of a row holds the row's max; then the row
 // broadcasts of lane 15 to rows 1 and 3 and of lane 31 to rows 2 and 3), read back from lane

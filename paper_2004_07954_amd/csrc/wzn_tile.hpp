@@ -518,7 +518,7 @@ __device__ __forceinline__ void row_tile(const RowArgs<T>& a, int64_t g0l, int64
   T fl0[NV];
 #pragma unroll
   for (int c = 0; c < NV; ++c) {
-    const T prev = __shfl_up(fh[c][K - 1], 1, 64);
+    const T prev = lane_prev(fh[c][K - 1]);
     fl0[c] = lane != 0 ? prev
                        : (wave == 0 ? EX[2 * c] + EX[2 * c + 1] : XF[(wave - 1) * NV + c]);
   }
