@@ -67,9 +67,6 @@ constexpr int CY_TX = 16, CY_TY = 16;
 __device__ __forceinline__ void char2_speeds(double rho, double mx, double my, double E,
                                              double gamma, double (&s)[6]);
 __device__ __forceinline__ void block_max6(double (&s)[6], unsigned long long* slot);
-template <int NT>
-__device__ __forceinline__ void block_max6_lds(const double (&s)[6], double* R,
-                                               unsigned long long* slot);
 
 // The sweep's alphas for the four fields (Sec. 4.3: one per field, |un - c|, |un|, |un|,
 // |un + c|) from three slots, a device array of four or one constant.
@@ -354,7 +351,7 @@ __global__ __launch_bounds__(NT) void char2_kernel(Char2Args a) {
       if (a.speed_next) char2_speeds(o[0], o[1], o[2], o[3], a.gamma, m);
     }
     // (the staged planes are no longer read: their LDS holds the reduction)
-    if (a.speed_next) block_max6_lds<NT>(m, &S[0][0], a.speed_next);
+    if (a.speed_next) block_max_lds<NT, 6>(m, &S[0][0], a.speed_next);
   }
 }
 
@@ -440,31 +437,6 @@ __device__ __forceinline__ void block_max6(double (&s)[6], unsigned long long* s
   if (threadIdx.x < 6) {
     const int f = threadIdx.x;
     atomic_max_pos(slot + f, fmax(fmax(red[f][0], red[f][1]), fmax(red[f][2], red[f][3])));
-  }
-}
-
-// Workgroup maxima of six per-thread values into slot[0..5] through LDS (R: 6 NT doubles no
-// thread reads any more): every thread writes its six, then 32 lanes per value each take the
-// max of eight (R[f][j + 32 q], conflict-free), and a 32-lane shuffle tree finishes.  Against
-// six 64-lane shuffle trees per thread (block_max6) this is 6 LDS writes per thread and the
-// tree on 192 threads.
-template <int NT>
-__device__ __forceinline__ void block_max6_lds(const double (&s)[6], double* R,
-                                               unsigned long long* slot) {
-  static_assert(NT == 256, "the tree assumes 256 threads");
-  const int tid = threadIdx.x;
-  __syncthreads();  // every read of R's previous contents is done
-#pragma unroll
-  for (int f = 0; f < 6; ++f) R[f * NT + tid] = s[f];
-  __syncthreads();
-  if (tid < 6 * 32) {
-    const int f = tid >> 5, j = tid & 31;
-    double m = R[f * NT + j];
-#pragma unroll
-    for (int q = 1; q < NT / 32; ++q) m = fmax(m, R[f * NT + j + 32 * q]);
-#pragma unroll
-    for (int off = 16; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
-    if (j == 0) atomic_max_pos(slot + f, m);
   }
 }
 

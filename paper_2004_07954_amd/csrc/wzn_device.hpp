@@ -242,44 +242,71 @@ __device__ __forceinline__ double slot_value(const unsigned long long* slot) {
   return __longlong_as_double((long long)(*slot));
 }
 
-// v of another lane by a DPP lane move of both 32-bit halves (CTRL, ROW_MASK as in the DPP
-// encoding; lanes of rows outside ROW_MASK keep their own v).
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ double dpp_move(double v) {
+// v of another lane by a DPP lane move of both 32-bit halves (CTRL as in the DPP encoding),
+// every lane written: a lane whose source lane does not exist for CTRL reads 0 (bound_ctrl),
+// so no copy of v has to be made first for lanes the move would leave alone.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move0(double v) {
   const long long b = __double_as_longlong(v);
-  const int lo = (int)b, hi = (int)(b >> 32);
-  const int lo2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROW_MASK, 0xF, false);
-  const int hi2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROW_MASK, 0xF, false);
+  const int lo2 = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, true);
+  const int hi2 = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
   return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi2 << 32) |
                                           (unsigned)lo2));
 }
 
-// The value of lane i - 1 in lane i (lane 0 keeps its own): one DPP wave_shr:1 lane move per
-// 32-bit half, in place of a shuffle through the LDS crossbar.  All 64 lanes must be active.
-__device__ __forceinline__ double lane_prev(double v) { return dpp_move<0x138, 0xF>(v); }
+// The value of lane i - 1 in lane i (lane 0 reads 0; its callers replace it): one DPP
+// wave_shr:1 lane move per 32-bit half, in place of a shuffle through the LDS crossbar.  All
+// 64 lanes must be active.
+__device__ __forceinline__ double lane_prev(double v) { return dpp_move0<0x138>(v); }
 __device__ __forceinline__ float lane_prev(float v) {
-  return __int_as_float(
-      __builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x138, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, true));
 }
 
-// Wave-wide max of 64 active lanes, returned in every lane: DPP lane moves (exchange within
-// quads, row half-mirror, row mirror: every lane of a row holds the row's max; then the row
-// broadcasts of lane 15 to rows 1 and 3 and of lane 31 to rows 2 and 3), read back from lane
-// 63.  VALU lane moves instead of the LDS crossbar of shuffles (ds_bpermute): six dependent
-// steps of a few cycles rather than of an LDS round trip.  max is exact and its order does
-// not matter, so every result is the same bits as a shuffle tree's.
+// Wave-wide max of 64 active lanes holding non-negative values, returned in every lane: DPP
+// lane moves (exchange within quads, row half-mirror, row mirror: every lane of a row holds
+// the row's max; then the row broadcasts of lane 15 to the next row and of lane 31 to rows 2
+// and 3), read back from lane 63.  A lane whose source does not exist takes max(v, 0) = v, so
+// the values must be >= 0 (wave speeds and magnitudes).  VALU lane moves instead of the LDS
+// crossbar of shuffles (ds_bpermute): six dependent steps of a few cycles rather than of an
+// LDS round trip.  max is exact and its order does not matter, so every result is the same
+// bits as a shuffle tree's.
 __device__ __forceinline__ double wave_max(double v) {
-  v = fmax(v, dpp_move<0xB1, 0xF>(v));   // quad_perm [1, 0, 3, 2]
-  v = fmax(v, dpp_move<0x4E, 0xF>(v));   // quad_perm [2, 3, 0, 1]
-  v = fmax(v, dpp_move<0x141, 0xF>(v));  // row_half_mirror
-  v = fmax(v, dpp_move<0x140, 0xF>(v));  // row_mirror
-  v = fmax(v, dpp_move<0x142, 0xA>(v));  // row_bcast:15
-  v = fmax(v, dpp_move<0x143, 0xC>(v));  // row_bcast:31
+  v = fmax(v, dpp_move0<0xB1>(v));   // quad_perm [1, 0, 3, 2]
+  v = fmax(v, dpp_move0<0x4E>(v));   // quad_perm [2, 3, 0, 1]
+  v = fmax(v, dpp_move0<0x141>(v));  // row_half_mirror
+  v = fmax(v, dpp_move0<0x140>(v));  // row_mirror
+  v = fmax(v, dpp_move0<0x142>(v));  // row_bcast:15
+  v = fmax(v, dpp_move0<0x143>(v));  // row_bcast:31
   const long long b = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_readlane((int)b, 63);
   const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
   return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
                                           (unsigned)lo));
+}
+
+// Workgroup maxima of NF per-thread non-negative values into slot[0 .. NF-1] through LDS
+// (R: NF * NT doubles that no thread reads any more): every thread writes its NF values, then
+// 32 lanes per value each take the max of NT / 32 of them (R[f][j + 32 q], conflict-free) and
+// a 32-lane shuffle tree finishes.  Against NF 64-lane trees on every wave this is NF LDS
+// writes per thread and one tree on 32 NF threads.  All NT threads must call it.
+template <int NT, int NF>
+__device__ __forceinline__ void block_max_lds(const double (&s)[NF], double* R,
+                                              unsigned long long* slot) {
+  static_assert(NT % 32 == 0 && 32 * NF <= NT, "one 32-lane group per value");
+  const int tid = threadIdx.x;
+  __syncthreads();  // every read of R's previous contents is done
+#pragma unroll
+  for (int f = 0; f < NF; ++f) R[f * NT + tid] = s[f];
+  __syncthreads();
+  if (tid < NF * 32) {
+    const int f = tid >> 5, j = tid & 31;
+    double m = R[f * NT + j];
+#pragma unroll
+    for (int q = 1; q < NT / 32; ++q) m = fmax(m, R[f * NT + j + 32 * q]);
+#pragma unroll
+    for (int off = 16; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+    if (j == 0) atomic_max_pos(slot + f, m);
+  }
 }
 
 }  // namespace wzn
