@@ -16,23 +16,44 @@
 namespace wzn {
 
 // max over cells of the largest wave speed into *slot (slot must be zero beforehand):
-// |u| + c for 1D Euler; (|u| + c, |v| + c) into (slot, slot_y) for 2D Euler.
+// |u| + c for 1D Euler; (|u| + c, |v| + c) into (slot, slot_y) for 2D Euler.  A grid-stride
+// loop that takes four cells per thread and iteration, their loads issued together.
+template <int NV, typename T>
+__device__ __forceinline__ void speed_of_cell(const T (&U)[NV], double gamma, double& sx,
+                                              double& sy) {
+  if constexpr (NV == 3) {
+    const double D[3] = {double(U[0]), double(U[1]), double(U[2])};
+    sx = fmax(sx, wave_speed_1d<SYS_EULER1>(D, 0.0, gamma));
+  } else {
+    double a, b;
+    wave_speeds_2d(U[0], U[1], U[2], U[3], gamma, a, b);
+    sx = fmax(sx, a);
+    sy = fmax(sy, b);
+  }
+}
+
 template <int NV, typename T>
 __global__ __launch_bounds__(256) void speed_max_kernel(const T* __restrict__ u, int64_t n,
                                                         double gamma, unsigned long long* slot,
                                                         unsigned long long* slot_y) {
+  constexpr int UNR = 4;
   double sx = 0.0, sy = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * 256) {
-    if constexpr (NV == 3) {
-      const double U[3] = {double(u[i]), double(u[n + i]), double(u[2 * n + i])};
-      sx = fmax(sx, wave_speed_1d<SYS_EULER1>(U, 0.0, gamma));
-    } else {
-      double a, b;
-      wave_speeds_2d(u[i], u[n + i], u[2 * n + i], u[3 * n + i], gamma, a, b);
-      sx = fmax(sx, a);
-      sy = fmax(sy, b);
-    }
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  for (; i + (UNR - 1) * stride < n; i += UNR * stride) {
+    T U[UNR][NV];
+#pragma unroll
+    for (int q = 0; q < UNR; ++q)
+#pragma unroll
+      for (int c = 0; c < NV; ++c) U[q][c] = u[c * n + i + q * stride];
+#pragma unroll
+    for (int q = 0; q < UNR; ++q) speed_of_cell<NV, T>(U[q], gamma, sx, sy);
+  }
+  for (; i < n; i += stride) {
+    T U[NV];
+#pragma unroll
+    for (int c = 0; c < NV; ++c) U[c] = u[c * n + i];
+    speed_of_cell<NV, T>(U, gamma, sx, sy);
   }
   __shared__ double red[2][4];
   sx = wave_max(sx);
@@ -63,8 +84,10 @@ int launch_zero_words(unsigned long long* p, int count, hipStream_t s) {
 template <typename T>
 int launch_speed_max(const T* u, int64_t n, int nv, double gamma, unsigned long long* slot,
                      unsigned long long* slot_y, hipStream_t s) {
+  // at most 512 workgroups: every workgroup ends with one atomic on the same word, and at
+  // 2048 of them finishing together those atomics cost more than the reduction itself
   int64_t blocks = (n + 255) / 256;
-  if (blocks > 2048) blocks = 2048;
+  if (blocks > 512) blocks = 512;
   if (nv == 3)
     hipLaunchKernelGGL((speed_max_kernel<3, T>), dim3((unsigned)blocks), dim3(256), 0, s, u, n,
                        gamma, slot, slot_y);
