@@ -436,13 +436,24 @@ __device__ __forceinline__ void row_tile(const RowArgs<T>& a, int64_t g0l, int64
             }
           }
         }
+        // (a.un is uniform: a branch around both forms, not a select per value)
+        if (a.un) {
 #pragma unroll
-        for (int c = 0; c < NV; ++c) {
+          for (int c = 0; c < NV; ++c) {
 #pragma unroll
-          for (int j = 0; j < K; ++j) {
-            const T b = T(a.rk_b) * Ureg[j][c];
-            Ureg[j][c] = a.un ? fma_t(T(a.rk_a), unv[c][j], b) : b;
-            asm volatile("" : "+v"(Ureg[j][c]));  // combine here, not in the epilogue
+            for (int j = 0; j < K; ++j) {
+              Ureg[j][c] = fma_t(T(a.rk_a), unv[c][j], T(a.rk_b) * Ureg[j][c]);
+              asm volatile("" : "+v"(Ureg[j][c]));  // combine here, not in the epilogue
+            }
+          }
+        } else {
+#pragma unroll
+          for (int c = 0; c < NV; ++c) {
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+              Ureg[j][c] = T(a.rk_b) * Ureg[j][c];
+              asm volatile("" : "+v"(Ureg[j][c]));
+            }
           }
         }
       }
@@ -556,7 +567,7 @@ __device__ __forceinline__ void row_tile(const RowArgs<T>& a, int64_t g0l, int64
   if constexpr (SPEED && SYS != SYS_EULER2X) {
 #pragma unroll
     for (int m = 0; m < K; ++m) {
-      if (c0 + m < n) {
+      if (full || c0 + m < n) {  // (no per-cell test in full tiles)
         double S[NV];
 #pragma unroll
         for (int c = 0; c < NV; ++c) S[c] = double(O[c][m]);
