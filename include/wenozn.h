@@ -327,6 +327,7 @@ int32_t wzn_rk3_run_2d_char(const wzn_params* p, void* u, void* stage, void* wor
  * global Lax-Friedrichs alpha (max |u| + c over the instance) and its own
  * dt = cfl dx[i] / max(|u| + c) of its U^n (Sec. 4.3).  p->bc_x applies to every instance;
  * alphas are always reduced (p->lf_alpha_x must be < 0).
+ *   total    cells of all instances together, at most 2^30 (WZN_ERR_SIZE beyond).
  *   stage    device scratch of 2 * 3 * total doubles.
  *   offsets  device int64 [batch + 1], non-decreasing, offsets[batch] == total; every instance
  *            must have 6 .. 2^30 cells (other or out-of-range instances are skipped unchanged).

@@ -106,3 +106,25 @@ def test_grid_with_a_2_31_element_plane(api):
     assert torch.isfinite(Lb[:, :3]).all() and torch.isfinite(Lb[:, -3:]).all()
     del Lb, Lv, big, small
     _free()
+
+
+def test_batched_launch_at_its_2_30_cell_limit(api):
+    """1024 instances of 2^20 cells in one batched launch: the concatenated state holds the
+    2^30 cells the launch accepts at most, so the third component starts at element 2^31.
+    Every instance starts from the same state, so every one must come out bit for bit equal
+    to the one-instance run of that state (same tile, exact maxima)."""
+    import torch
+    M, B = 1 << 20, 1024
+    note("batched run of %d instances of 2^20 cells (%d cells, the third component at 2^31)"
+         % (B, B * M))
+    u0, dx = I.shu_osher_like(M)
+    one = torch.tensor(u0, dtype=torch.float64, device="cuda")
+    big = one.repeat(1, B)
+    assert 2 * B * M == (1 << 31)
+    offs = torch.arange(0, B + 1, dtype=torch.int64, device="cuda") * M
+    dxs = torch.full((B,), dx, dtype=torch.float64, device="cuda")
+    api.batched_rk3_run_1d(big, offs, dxs, 1)
+    api.rk3_run_1d(one, dx, 1, cfl=0.5)
+    assert bool((big.view(3, B, M) == one[:, None, :]).all())
+    del big, one, offs, dxs
+    _free()
